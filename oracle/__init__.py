@@ -1,0 +1,144 @@
+"""Reference oracle for nested multi-level reductions -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The GPU library never does, and this package
+imports nothing from it.  The arithmetic lives in ``oracle.c`` (plain
+sequential C nested loops, see ``oracle.h`` for the definition and the
+readings of the paper it follows); this file only builds and calls it.
+
+Every function here is pinned by ``tests/test_oracle.py`` against closed
+forms, exactly rounded sums (``math.fsum``), numpy library reductions,
+brute force on tiny nests and invariants; nothing is left "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NONE, SUM, MIN, MAX, ARGMIN, ARGMAX = 0, 1, 2, 3, 4, 5
+I32, F32, BF16 = 0, 1, 2
+OUT_I32, OUT_I64, OUT_F64 = 0, 1, 2
+_OUT_NP = {OUT_I32: np.int32, OUT_I64: np.int64, OUT_F64: np.float64}
+_IN_NP = {I32: np.int32, F32: np.float32, BF16: np.uint16}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc -O2 (no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.oracle_out_kind.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int]
+        lib.oracle_out_kind.restype = ctypes.c_int
+        lib.oracle_n_out.argtypes = [ctypes.c_int, i64p, ip]
+        lib.oracle_n_out.restype = ctypes.c_int64
+        lib.oracle_reduce_range.argtypes = [ctypes.c_int, i64p, ip, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_reduce_range.restype = ctypes.c_int
+        lib.oracle_abs_sum_range.argtypes = lib.oracle_reduce_range.argtypes
+        lib.oracle_abs_sum_range.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _arrays(extents, ops):
+    d = len(extents)
+    e = (ctypes.c_int64 * d)(*[int(x) for x in extents])
+    o = (ctypes.c_int * d)(*[int(x) for x in ops])
+    return d, e, o
+
+
+def out_kind(extents, ops, dtype) -> int:
+    d, e, o = _arrays(extents, ops)
+    k = _load().oracle_out_kind(d, e, o, int(dtype))
+    if k < 0:
+        raise ValueError("nest not defined for the oracle")
+    return k
+
+
+def n_out(extents, ops) -> int:
+    d, e, o = _arrays(extents, ops)
+    k = _load().oracle_n_out(d, e, o)
+    if k < 0:
+        raise ValueError("nest not defined for the oracle")
+    return int(k)
+
+
+def _check_input(x: np.ndarray, extents, dtype):
+    want = _IN_NP[dtype]
+    if x.dtype != want:
+        raise TypeError(f"input dtype {x.dtype}, expected {np.dtype(want)}")
+    if x.size != int(np.prod(extents, dtype=np.int64)):
+        raise ValueError("input size does not match the extents")
+    if not x.flags.c_contiguous:
+        raise ValueError("input must be C-contiguous")
+
+
+def reduce(x: np.ndarray, extents, ops, dtype, threads: int = 1, o_begin: int = 0,
+           o_end: int | None = None) -> np.ndarray:
+    """Outputs [o_begin, o_end) of the nest over the row-major input ``x``
+    (int32, float32, or bfloat16 bit patterns as uint16)."""
+    _check_input(x, extents, dtype)
+    kind = out_kind(extents, ops, dtype)
+    total = n_out(extents, ops)
+    if o_end is None:
+        o_end = total
+    out = np.empty(o_end - o_begin, _OUT_NP[kind])
+    d, e, o = _arrays(extents, ops)
+    rc = _load().oracle_reduce_range(d, e, o, int(dtype), x.ctypes.data, out.ctypes.data,
+                                     int(o_begin), int(o_end), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the nest or range")
+    return out
+
+
+def abs_sum(x: np.ndarray, extents, ops, dtype, threads: int = 1, o_begin: int = 0,
+            o_end: int | None = None) -> np.ndarray:
+    """Sum of |a| over each output's reduced block (float nests): the scale of
+    the accuracy bound."""
+    _check_input(x, extents, dtype)
+    total = n_out(extents, ops)
+    if o_end is None:
+        o_end = total
+    out = np.empty(o_end - o_begin, np.float64)
+    d, e, o = _arrays(extents, ops)
+    rc = _load().oracle_abs_sum_range(d, e, o, int(dtype), x.ctypes.data, out.ctypes.data,
+                                      int(o_begin), int(o_end), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the nest or range")
+    return out
+
+
+def within_tolerance(got: np.ndarray, ref: np.ndarray, abs_sum_ref: np.ndarray, rel: float = 1e-6):
+    """Float acceptance rule: |got - ref| <= rel * max(|ref|, 2^-24 * sum|a|).
+    Returns (ok, max plain relative error, max scaled error)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.maximum(np.abs(ref), abs_sum_ref * 2.0**-24)
+    err = np.abs(got - ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        plain = np.where(ref != 0, err / np.abs(ref), np.where(err == 0, 0.0, np.inf))
+        scaled = np.where(scale > 0, err / scale, np.where(err == 0, 0.0, np.inf))
+    ok = bool(np.all(scaled <= rel))
+    return ok, float(plain.max(initial=0.0)), float(scaled.max(initial=0.0))
