@@ -1,0 +1,241 @@
+"""Hierarchical nested reductions on MI355X (gfx950): Python binding of libhp.so.
+
+Argument marshalling only: every step of the reduction runs in the HIP kernels of
+``libhp.so``; torch supplies device memory and streams.  The library must have
+been built (``python paper_2309_01906_amd/build.py`` or ``__graft_entry__.build()``);
+without it every call raises ``RuntimeError`` -- there is no fallback path.
+
+Level maps are written per loop level as a string of scope letters, outermost
+first: ``"G"`` grid (workgroups), ``"W"`` workgroup (waves), ``"V"`` wavefront
+(lanes), ``"L"`` lane (serial), e.g. ``["G", "W", "VL"]``; optionally with unit
+counts: ``("GW", {"G": 16, "W": 8})``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhp.so")
+
+MAX_DEPTH = 8
+NONE, SUM, MIN, MAX, ARGMIN, ARGMAX = 0, 1, 2, 3, 4, 5
+I32, F32, BF16, I64, F64 = 0, 1, 2, 3, 4
+SCOPE = {"G": 1, "W": 2, "V": 4, "L": 8}
+AXIS = {"G": 0, "W": 1, "V": 2}
+FLAG_OUT_F32, FLAG_SCALAR, FLAG_NO_XCD, FLAG_TEMPORAL = 0x1, 0x2, 0x4, 0x8
+OP_NAMES = {"NONE": NONE, "SUM": SUM, "MIN": MIN, "MAX": MAX, "ARGMIN": ARGMIN, "ARGMAX": ARGMAX}
+STATUS = ["HP_OK", "HP_EINVAL", "HP_EUNSUPPORTED", "HP_ENOMEM", "HP_EDEVICE", "HP_EAGAIN",
+          "HP_ETOOBIG", "HP_ENOTREADY", "HP_ECANCELED", "HP_ESTATE"]
+
+
+class HPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        self.status_name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{self.status_name}: {msg}")
+
+
+class Nest(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("op", ctypes.c_int32 * MAX_DEPTH), ("extent", ctypes.c_int64 * MAX_DEPTH)]
+
+
+class LevelMap(ctypes.Structure):
+    _fields_ = [("scopes", ctypes.c_uint32 * MAX_DEPTH), ("units", (ctypes.c_uint32 * 3) * MAX_DEPTH)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("out_dtype", ctypes.c_int32), ("n_out", ctypes.c_int64),
+                ("out_bytes", ctypes.c_size_t), ("in_elems", ctypes.c_int64), ("in_bytes", ctypes.c_size_t),
+                ("grid", ctypes.c_int64), ("waves", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("gsplit", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t), ("lds_bytes", ctypes.c_size_t),
+                ("scopes", ctypes.c_uint32 * MAX_DEPTH), ("units", (ctypes.c_uint32 * 3) * MAX_DEPTH),
+                ("strips", ctypes.c_int64 * MAX_DEPTH), ("nseg", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2309_01906_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, st = ctypes.c_void_p, ctypes.c_int
+        L.hp_plan_inspect.argtypes = [ctypes.POINTER(Nest), ctypes.POINTER(LevelMap), ctypes.c_uint32,
+                                      ctypes.POINTER(PlanInfo)]
+        L.hp_plan_inspect.restype = st
+        L.hp_plan.argtypes = [ctypes.POINTER(Nest), ctypes.POINTER(LevelMap), ctypes.c_uint32,
+                              ctypes.POINTER(vp)]
+        L.hp_plan.restype = st
+        L.hp_plan_info_get.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.hp_plan_info_get.restype = st
+        L.hp_run.argtypes = [vp, vp, vp, vp]
+        L.hp_run.restype = st
+        L.hp_destroy.argtypes = [vp]
+        L.hp_destroy.restype = st
+        L.hp_last_error.argtypes = []
+        L.hp_last_error.restype = ctypes.c_char_p
+        L.hp_status_str.argtypes = [st]
+        L.hp_status_str.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        raise HPError(status, lib().hp_last_error().decode(errors="replace"))
+
+
+def _op(o):
+    return OP_NAMES[o.upper()] if isinstance(o, str) else int(o)
+
+
+def make_nest(extents, ops, dtype) -> Nest:
+    n = Nest()
+    if len(extents) != len(ops) or not 1 <= len(extents) <= MAX_DEPTH:
+        raise ValueError("extents and ops must have the same length, 1..8")
+    n.depth = len(extents)
+    n.dtype = int(dtype)
+    for i, (e, o) in enumerate(zip(extents, ops)):
+        n.extent[i] = int(e)
+        n.op[i] = _op(o)
+    return n
+
+
+def make_map(level_map) -> LevelMap | None:
+    if level_map is None:
+        return None
+    m = LevelMap()
+    for i, lv in enumerate(level_map):
+        units = {}
+        if isinstance(lv, (tuple, list)):
+            lv, units = lv
+        s = 0
+        for ch in lv.replace("+", "").upper():
+            s |= SCOPE[ch]
+        m.scopes[i] = s
+        for k, v in units.items():
+            m.units[i][AXIS[k.upper()]] = int(v)
+    return m
+
+
+def _info_dict(inf: PlanInfo) -> dict:
+    d = inf.depth
+    names = "GWVL"
+    return {
+        "depth": d, "out_dtype": inf.out_dtype, "n_out": inf.n_out, "out_bytes": inf.out_bytes,
+        "in_elems": inf.in_elems, "in_bytes": inf.in_bytes, "grid": inf.grid, "waves": inf.waves,
+        "chunk": inf.chunk, "gsplit": inf.gsplit, "workspace_bytes": inf.workspace_bytes,
+        "lds_bytes": inf.lds_bytes, "nseg": inf.nseg,
+        "map": ["".join(names[b] for b in range(4) if inf.scopes[i] >> b & 1) for i in range(d)],
+        "units": [tuple(inf.units[i][a] for a in range(3)) for i in range(d)],
+        "strips": [inf.strips[i] for i in range(d)],
+    }
+
+
+def inspect(extents, ops, dtype, level_map=None, flags: int = 0) -> dict:
+    """Plan without a device: validation and launch geometry (host only)."""
+    n = make_nest(extents, ops, dtype)
+    m = make_map(level_map)
+    inf = PlanInfo()
+    check(lib().hp_plan_inspect(ctypes.byref(n), ctypes.byref(m) if m is not None else None,
+                                flags, ctypes.byref(inf)))
+    return _info_dict(inf)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def torch_out_dtype(code):
+    torch = _torch()
+    return {I32: torch.int32, I64: torch.int64, F32: torch.float32, F64: torch.float64}[code]
+
+
+def dtype_of(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.int32:
+        return I32
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return BF16
+    raise TypeError(f"unsupported input dtype {t.dtype}")
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Plan:
+    """A planned nest (hp_plan).  ``run`` launches it on a torch stream."""
+
+    def __init__(self, extents, ops, dtype, level_map=None, flags: int = 0):
+        self._h = ctypes.c_void_p()
+        self.extents = tuple(int(e) for e in extents)
+        self.ops = tuple(_op(o) for o in ops)
+        self.dtype = int(dtype)
+        n = make_nest(extents, ops, dtype)
+        m = make_map(level_map)
+        check(lib().hp_plan(ctypes.byref(n), ctypes.byref(m) if m is not None else None, flags,
+                            ctypes.byref(self._h)))
+        inf = PlanInfo()
+        check(lib().hp_plan_info_get(self._h, ctypes.byref(inf)))
+        self.info = _info_dict(inf)
+
+    def empty_out(self, device):
+        return _torch().empty(self.info["n_out"], dtype=torch_out_dtype(self.info["out_dtype"]), device=device)
+
+    def run(self, inp, out=None, stream=None):
+        torch = _torch()
+        if not inp.is_cuda:
+            raise ValueError("input must be a device tensor")
+        if not inp.is_contiguous():
+            raise ValueError("input must be contiguous")
+        if inp.numel() != self.info["in_elems"] or dtype_of(inp) != self.dtype:
+            raise ValueError("input does not match the planned nest")
+        if out is None:
+            out = self.empty_out(inp.device)
+        if out.numel() != self.info["n_out"] or out.dtype != torch_out_dtype(self.info["out_dtype"]):
+            raise ValueError("output does not match the plan")
+        check(lib().hp_run(self._h, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                           _stream_handle(stream)))
+        return out
+
+    __call__ = run
+
+    def close(self):
+        if self._h:
+            check(lib().hp_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.hp_destroy(self._h)
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def reduce(inp, extents, ops, level_map=None, flags: int = 0, stream=None):
+    """One-shot: plan, run, return the output tensor (the plan is freed after the
+    stream has finished with it)."""
+    p = Plan(extents, ops, dtype_of(inp), level_map, flags)
+    out = p.run(inp, stream=stream)
+    _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    p.close()
+    return out

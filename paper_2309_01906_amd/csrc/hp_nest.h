@@ -1,0 +1,869 @@
+// Nested multi-level reduction: device templates for gfx950 (CDNA4, wave64).
+//
+// One kernel template executes any planned nest.  Every loop level owns a slice of
+// the hardware: a factor of the workgroup index (G), of the wave index (W) and of
+// the lane index (V); the rest of its iterations are serial strips (L).  Inside a
+// workgroup the reducing levels are walked in two loops whose counters are the same
+// for every thread (so they live in scalar registers):
+//   - the innermost segment (a run of levels with one operator that can be folded
+//     as a single reduction) is a stream: U chunks are loaded back to back, each
+//     one 16-byte load per lane at thread_base + strip_offset, then folded into the
+//     lane's private partial (section 3.6's private partial sum);
+//   - the levels outside it form an odometer; each time a segment's last strip is
+//     done its partials are combined and fed to the enclosing level's operator.
+// Combines follow the paper's recursive reduction (section 2: every level collects
+// its siblings' results through its cheapest means):
+//   lanes       xor butterfly: DPP quad_perm / row_shr / row_shl, ds_swizzle and
+//               ds_bpermute (section 3.7's shuffle; a wave64 runs in lockstep, so no
+//               masks or warp syncs are needed);
+//   waves       one LDS slot per wave, s_barrier, every wave folds its group's slots
+//               in wave order (section 3.7's fallback through memory one level up);
+//   workgroups  a partial per workgroup in global memory and an agent-scope atomic
+//               ticket; the last workgroup folds all partials in index order (the
+//               grid has no barrier across its units, sections 1 and 3.2).
+// Float sums keep an fp32 (sum, error) pair per lane, extended by TwoSum for every
+// element, and use fp64 only when partials of several workgroups are folded and for
+// the output.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hp_internal.h"
+
+namespace hp {
+
+// clang vector types (nontemporal loads need native vectors, not HIP's wrappers)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// cross-lane moves: the value held by lane (lane ^ mask), mask in {1,2,4,8,16,32}
+
+__device__ __forceinline__ int xor_move(int v, int mask, int lane) {
+  if (mask == 1) return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  if (mask == 2) return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  if (mask == 4) {
+    const int dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false);  // row_shr:4, from lane-4
+    const int up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0xF, false);  // row_shl:4, from lane+4
+    return (lane & 4) ? dn : up;
+  }
+  if (mask == 8) {
+    const int dn = __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    const int up = __builtin_amdgcn_update_dpp(v, v, 0x108, 0xF, 0xF, false);  // row_shl:8
+    return (lane & 8) ? dn : up;
+  }
+  if (mask == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // bitmask mode: and 0x1F, xor 0x10
+  return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+}
+
+__device__ __forceinline__ float xor_move_f(float v, int mask, int lane) {
+  return __int_as_float(xor_move(__float_as_int(v), mask, lane));
+}
+__device__ __forceinline__ long long xor_move_l(long long v, int mask, int lane) {
+  const int lo = xor_move((int)(uint32_t)(unsigned long long)v, mask, lane);
+  const int hi = xor_move((int)(uint32_t)((unsigned long long)v >> 32), mask, lane);
+  return (long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double xor_move_d(double v, int mask, int lane) {
+  return __longlong_as_double(xor_move_l(__double_as_longlong(v), mask, lane));
+}
+
+// Error-free sum (Knuth's TwoSum): s + e == a + b exactly, s = fl(a + b).
+template <class F>
+__device__ __forceinline__ void two_sum(F a, F b, F& s, F& e) {
+  s = a + b;
+  const F bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// ---------------------------------------------------------------------------
+// carriers
+
+struct FAcc {
+  float s, c;  // value = s + c; c collects the exact rounding errors of s
+};
+struct IAcc {
+  long long v;
+  int i;  // ARG levels: iteration index of v
+  int pad;
+};
+
+template <class RawT>
+struct FloatT {
+  using Raw = RawT;
+  using Acc = FAcc;
+  static constexpr bool kFloat = true;
+  __device__ static __forceinline__ Acc identity(int) { return Acc{0.f, 0.f}; }
+  __device__ static __forceinline__ void add(Acc& a, float x, long long, int) {
+    float s, e;
+    two_sum(a.s, x, s, e);
+    a.s = s;
+    a.c += e;
+  }
+  // symmetric in (a, b), so both partners of a butterfly step get identical bits
+  __device__ static __forceinline__ Acc merge(Acc a, Acc b, int) {
+    float s, e;
+    two_sum(a.s, b.s, s, e);
+    const float c = (a.c + b.c) + e;
+    const float s2 = s + c;
+    return Acc{s2, c - (s2 - s)};
+  }
+  __device__ static __forceinline__ Acc shfl(Acc a, int mask, int lane) {
+    return Acc{xor_move_f(a.s, mask, lane), xor_move_f(a.c, mask, lane)};
+  }
+  __device__ static __forceinline__ void put(char* base, long long slot, Acc a) {
+    f32x2 v;
+    v.x = a.s;
+    v.y = a.c;
+    *reinterpret_cast<f32x2*>(base + slot * kSlotBytes) = v;
+  }
+  __device__ static __forceinline__ Acc get(const char* base, long long slot) {
+    const f32x2 v = *reinterpret_cast<const f32x2*>(base + slot * kSlotBytes);
+    return Acc{v.x, v.y};
+  }
+};
+
+struct IntT {
+  using Raw = int32_t;
+  using Acc = IAcc;
+  static constexpr bool kFloat = false;
+  __device__ static __forceinline__ Acc identity(int op) {
+    switch (op) {
+      case HP_OP_MIN: return Acc{0x7FFFFFFFFFFFFFFFll, 0, 0};
+      case HP_OP_MAX: return Acc{(long long)0x8000000000000000ull, 0, 0};
+      case HP_OP_ARGMIN: return Acc{0x7FFFFFFFFFFFFFFFll, 0x7FFFFFFF, 0};
+      case HP_OP_ARGMAX: return Acc{(long long)0x8000000000000000ull, 0x7FFFFFFF, 0};
+      default: return Acc{0, 0, 0};
+    }
+  }
+  // fold child value x with iteration index t into the carrier
+  __device__ static __forceinline__ void add(Acc& a, long long x, long long t, int op) {
+    switch (op) {
+      case HP_OP_SUM: a.v = (long long)((unsigned long long)a.v + (unsigned long long)x); break;
+      case HP_OP_MIN: a.v = x < a.v ? x : a.v; break;
+      case HP_OP_MAX: a.v = x > a.v ? x : a.v; break;
+      case HP_OP_ARGMIN:
+        if (x < a.v || (x == a.v && (int)t < a.i)) {
+          a.v = x;
+          a.i = (int)t;
+        }
+        break;
+      case HP_OP_ARGMAX:
+        if (x > a.v || (x == a.v && (int)t < a.i)) {
+          a.v = x;
+          a.i = (int)t;
+        }
+        break;
+      default: break;
+    }
+  }
+  // lexicographic (value, index) for ARG: ties keep the smaller index
+  __device__ static __forceinline__ Acc merge(Acc a, Acc b, int op) {
+    switch (op) {
+      case HP_OP_SUM: a.v = (long long)((unsigned long long)a.v + (unsigned long long)b.v); return a;
+      case HP_OP_MIN: a.v = b.v < a.v ? b.v : a.v; return a;
+      case HP_OP_MAX: a.v = b.v > a.v ? b.v : a.v; return a;
+      case HP_OP_ARGMIN: return (b.v < a.v || (b.v == a.v && b.i < a.i)) ? b : a;
+      case HP_OP_ARGMAX: return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a;
+      default: return a;
+    }
+  }
+  __device__ static __forceinline__ long long emit(Acc a, int op) {
+    return (op == HP_OP_ARGMIN || op == HP_OP_ARGMAX) ? (long long)a.i : a.v;
+  }
+  __device__ static __forceinline__ Acc shfl(Acc a, int mask, int lane) {
+    Acc r;
+    r.v = xor_move_l(a.v, mask, lane);
+    r.i = xor_move(a.i, mask, lane);
+    r.pad = 0;
+    return r;
+  }
+  __device__ static __forceinline__ void put(char* base, long long slot, Acc a) {
+    long long* q = reinterpret_cast<long long*>(base + slot * kSlotBytes);
+    q[0] = a.v;
+    q[1] = (long long)(uint32_t)a.i;
+  }
+  __device__ static __forceinline__ Acc get(const char* base, long long slot) {
+    const long long* q = reinterpret_cast<const long long*>(base + slot * kSlotBytes);
+    return Acc{q[0], (int)q[1], 0};
+  }
+};
+
+// ---------------------------------------------------------------------------
+// chunk loads: C consecutive elements of the innermost level; 16 bytes for the
+// vector chunk (aligned: the plan only picks it when the extent allows)
+
+template <class Raw, int C>
+struct Chunk;
+template <>
+struct Chunk<float, 4> { using V = f32x4; };
+template <>
+struct Chunk<float, 1> { using V = float; };
+template <>
+struct Chunk<int32_t, 4> { using V = i32x4; };
+template <>
+struct Chunk<int32_t, 1> { using V = int; };
+template <>
+struct Chunk<uint16_t, 8> { using V = u32x4; };
+template <>
+struct Chunk<uint16_t, 1> { using V = unsigned short; };
+
+template <class V>
+__device__ __forceinline__ V load_chunk(const void* p, bool nt) {
+  const V* q = reinterpret_cast<const V*>(p);
+  return nt ? __builtin_nontemporal_load(q) : *q;
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// element that leaves a carrier unchanged (for lanes whose chunk is masked out);
+// for ARG the masked chunk's index is beyond the extent, so real ties still win
+template <class T, int OP>
+__device__ __forceinline__ float masked_f(float x, bool ok) {
+  return ok ? x : 0.0f;
+}
+template <int OP>
+__device__ __forceinline__ int masked_i(int x, bool ok) {
+  constexpr int id = (OP == HP_OP_MIN || OP == HP_OP_ARGMIN) ? 0x7FFFFFFF
+                     : (OP == HP_OP_MAX || OP == HP_OP_ARGMAX) ? (int)0x80000000
+                                                               : 0;
+  return ok ? x : id;
+}
+
+template <class T, int C, int OP>
+struct AddChunk;
+template <int OP>
+struct AddChunk<FloatT<float>, 4, OP> {
+  __device__ static __forceinline__ void run(FAcc& a, f32x4 x, long long, bool ok) {
+    FloatT<float>::add(a, masked_f<FloatT<float>, OP>(x.x, ok), 0, 0);
+    FloatT<float>::add(a, masked_f<FloatT<float>, OP>(x.y, ok), 0, 0);
+    FloatT<float>::add(a, masked_f<FloatT<float>, OP>(x.z, ok), 0, 0);
+    FloatT<float>::add(a, masked_f<FloatT<float>, OP>(x.w, ok), 0, 0);
+  }
+};
+template <int OP>
+struct AddChunk<FloatT<float>, 1, OP> {
+  __device__ static __forceinline__ void run(FAcc& a, float x, long long, bool ok) {
+    FloatT<float>::add(a, masked_f<FloatT<float>, OP>(x, ok), 0, 0);
+  }
+};
+template <int OP>
+struct AddChunk<FloatT<uint16_t>, 8, OP> {
+  __device__ static __forceinline__ void run(FAcc& a, u32x4 x, long long, bool ok) {
+    const u32x4 m = ok ? x : u32x4{0u, 0u, 0u, 0u};
+    FloatT<uint16_t>::add(a, bf16_lo(m.x), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_hi(m.x), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_lo(m.y), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_hi(m.y), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_lo(m.z), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_hi(m.z), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_lo(m.w), 0, 0);
+    FloatT<uint16_t>::add(a, bf16_hi(m.w), 0, 0);
+  }
+};
+template <int OP>
+struct AddChunk<FloatT<uint16_t>, 1, OP> {
+  __device__ static __forceinline__ void run(FAcc& a, unsigned short x, long long, bool ok) {
+    FloatT<uint16_t>::add(a, bf16_lo(ok ? x : 0), 0, 0);
+  }
+};
+template <int OP>
+struct AddChunk<IntT, 4, OP> {
+  __device__ static __forceinline__ void run(IAcc& a, i32x4 x, long long t, bool ok) {
+    IntT::add(a, masked_i<OP>(x.x, ok), t, OP);
+    IntT::add(a, masked_i<OP>(x.y, ok), t + 1, OP);
+    IntT::add(a, masked_i<OP>(x.z, ok), t + 2, OP);
+    IntT::add(a, masked_i<OP>(x.w, ok), t + 3, OP);
+  }
+};
+template <int OP>
+struct AddChunk<IntT, 1, OP> {
+  __device__ static __forceinline__ void run(IAcc& a, int x, long long t, bool ok) {
+    IntT::add(a, masked_i<OP>(x, ok), t, OP);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// per-thread view of one workgroup's share
+
+template <int KD>
+struct Thread {
+  int w, lane;
+  int lim[KD];   // strips on which this thread's unit of level m has t < e
+  int targ[KD];  // first iteration of level m for this thread (used by ARG levels)
+  int limc[KD];  // lim of inner dim k
+};
+
+// Walk the innermost segment for one setting of the outer levels: U chunk loads in
+// flight, then folded in order.  ND is the number of the segment's levels that have
+// more than one strip (1, 2, or any up to KD).  With CHECK, lanes whose chunk is
+// masked out load element 0 instead (always in bounds) and fold the identity, so
+// the loads are never predicated and stay in flight together.
+template <class T, int C, int OP, int U, int ND, int KD, bool CHECK>
+__device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typename T::Raw* __restrict__ in,
+                                                  long long base, bool valid, const Thread<KD>& th) {
+  using Acc = typename T::Acc;
+  using V = typename Chunk<typename T::Raw, C>::V;
+  using Raw = typename T::Raw;
+  constexpr bool kArg = (OP == HP_OP_ARGMIN || OP == HP_OP_ARGMAX);
+  const bool nt = !(P.flags & HP_FLAG_TEMPORAL);
+  const int nid = P.nid;
+  Acc a = T::identity(OP);
+  long long t_first = 0, span_last = 0;
+  if constexpr (kArg) {
+    const int dl = P.depth - 1;
+#pragma unroll
+    for (int m = 0; m < KD; ++m)
+      if (m == dl) {
+        t_first = th.targ[m];
+        span_last = P.last_dim_is_last_level ? P.lv[m].span : 0;
+      }
+  }
+  const Raw* __restrict__ row = in + base;
+  const long long F = P.inner_iters;
+  if constexpr (ND == 1) {
+    // one strided dimension (or none): chunk f sits at f * sstride.  Full batches
+    // are straight-line code (U loads, then U folds); the tail goes one by one.
+    const long long ss = nid > 0 ? P.id_sstride[0] : 0;
+    const bool rag = nid > 0 && P.id_ragged[0];
+    const int lim = th.limc[0];
+    const long long Ffull = F - F % U;
+    long long f0 = 0;
+    for (; f0 < Ffull; f0 += U) {
+      V x[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long f = f0 + u;
+        ok[u] = true;
+        if constexpr (CHECK) ok[u] = valid && (!rag || f < lim);
+        x[u] = load_chunk<V>(ok[u] ? row + f * ss : in, nt);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) AddChunk<T, C, OP>::run(a, x[u], t_first + (f0 + u) * span_last, ok[u]);
+    }
+    for (; f0 < F; ++f0) {
+      bool ok = true;
+      if constexpr (CHECK) ok = valid && (!rag || f0 < lim);
+      const V x = load_chunk<V>(ok ? row + f0 * ss : in, nt);
+      AddChunk<T, C, OP>::run(a, x, t_first + f0 * span_last, ok);
+    }
+  } else if constexpr (ND == 2) {
+    const long long S1 = P.id_strips[1];
+    const long long ss0 = P.id_sstride[0], ss1 = P.id_sstride[1];
+    const bool rag0 = P.id_ragged[0], rag1 = P.id_ragged[1];
+    const int lim0 = th.limc[0], lim1 = th.limc[1];
+    long long s0 = 0, s1 = 0, soff = 0;
+    for (long long f0 = 0; f0 < F; f0 += U) {
+      const int nu = (F - f0) < U ? (int)(F - f0) : U;
+      V x[U];
+      bool ok[U];
+      long long sl[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ok[u] = true;
+        if constexpr (CHECK) ok[u] = valid && (!rag0 || s0 < lim0) && (!rag1 || s1 < lim1);
+        sl[u] = s1;
+        if (u < nu) {
+          x[u] = load_chunk<V>(ok[u] ? row + soff : in, nt);
+          soff += ss1;
+          if (++s1 == S1) {
+            s1 = 0;
+            ++s0;
+            soff += ss0 - S1 * ss1;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (u < nu) AddChunk<T, C, OP>::run(a, x[u], t_first + sl[u] * span_last, ok[u]);
+    }
+  } else {
+    int s[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) s[k] = 0;
+    long long soff = 0;
+    for (long long f0 = 0; f0 < F; f0 += U) {
+      const int nu = (F - f0) < U ? (int)(F - f0) : U;
+      V x[U];
+      bool ok[U];
+      int sl[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        bool v = valid;
+#pragma unroll
+        for (int k = 0; k < KD; ++k)
+          if (k < nid && P.id_ragged[k]) v = v && (s[k] < th.limc[k]);
+        ok[u] = v;
+        sl[u] = 0;
+#pragma unroll
+        for (int k = 0; k < KD; ++k)
+          if (k == nid - 1) sl[u] = s[k];
+        if (u < nu) {
+          x[u] = load_chunk<V>(ok[u] ? row + soff : in, nt);
+          bool carry = true;
+#pragma unroll
+          for (int k = KD - 1; k >= 0; --k) {
+            if (carry && k < nid) {
+              ++s[k];
+              soff += P.id_sstride[k];
+              if (s[k] == P.id_strips[k]) {
+                s[k] = 0;
+                soff -= P.id_strips[k] * P.id_sstride[k];
+              } else {
+                carry = false;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (u < nu) AddChunk<T, C, OP>::run(a, x[u], t_first + (long long)sl[u] * span_last, ok[u]);
+    }
+  }
+  return a;
+}
+
+template <class T, int C, int OP, int U, int KD>
+__device__ __forceinline__ typename T::Acc stream_any(const DevPlan& P, const typename T::Raw* __restrict__ in,
+                                                      long long base, bool valid, const Thread<KD>& th) {
+  // every lane of the wave valid and no ragged level: no masking needed
+  bool rag = false;
+#pragma unroll
+  for (int k = 0; k < KD; ++k)
+    if (k < P.nid && P.id_ragged[k]) rag = true;
+  const bool check = rag || __builtin_amdgcn_ballot_w64(!valid) != 0;
+  if (P.nid <= 1) {
+    if (check) return stream<T, C, OP, U, 1, KD, true>(P, in, base, valid, th);
+    return stream<T, C, OP, U, 1, KD, false>(P, in, base, valid, th);
+  }
+  if (P.nid == 2) {
+    if (check) return stream<T, C, OP, U, 2, KD, true>(P, in, base, valid, th);
+    return stream<T, C, OP, U, 2, KD, false>(P, in, base, valid, th);
+  }
+  return stream<T, C, OP, U, KD, KD, true>(P, in, base, valid, th);
+}
+
+template <class T, int C, int U, int KD>
+struct InnerStream;
+template <class R, int C, int U, int KD>
+struct InnerStream<FloatT<R>, C, U, KD> {
+  __device__ static __forceinline__ FAcc run(const DevPlan& P, const R* __restrict__ in, long long base, bool valid,
+                                             const Thread<KD>& th) {
+    return stream_any<FloatT<R>, C, HP_OP_SUM, U, KD>(P, in, base, valid, th);
+  }
+};
+template <int C, int U, int KD>
+struct InnerStream<IntT, C, U, KD> {
+  __device__ static __forceinline__ IAcc run(const DevPlan& P, const int32_t* __restrict__ in, long long base,
+                                             bool valid, const Thread<KD>& th) {
+    switch (P.seg[P.nseg - 1].op) {
+      case HP_OP_MIN: return stream_any<IntT, C, HP_OP_MIN, U, KD>(P, in, base, valid, th);
+      case HP_OP_MAX: return stream_any<IntT, C, HP_OP_MAX, U, KD>(P, in, base, valid, th);
+      case HP_OP_ARGMIN: return stream_any<IntT, C, HP_OP_ARGMIN, U, KD>(P, in, base, valid, th);
+      case HP_OP_ARGMAX: return stream_any<IntT, C, HP_OP_ARGMAX, U, KD>(P, in, base, valid, th);
+      default: return stream_any<IntT, C, HP_OP_SUM, U, KD>(P, in, base, valid, th);
+    }
+  }
+};
+
+// Combine a segment's partials across its lanes (butterfly) and waves (LDS).
+// Afterwards every lane of a group holds the group's value.
+template <class T, int KD>
+__device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const DevSeg& S, typename T::Acc a,
+                                                       const Thread<KD>& th, char* lds) {
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if ((S.vmask >> b) & 1u) a = T::merge(a, T::shfl(a, 1 << b, th.lane), S.op);
+  if (S.wmask) {
+    const int lanes = P.lds_slot_lanes;
+    const int lidx = lanes == 1 ? 0 : (int)(th.lane & S.lds_lanes);
+    __syncthreads();  // earlier readers of the slots are done
+    if ((th.lane & ~(int)S.lds_lanes & 63) == 0) T::put(lds, th.w * lanes + lidx, a);
+    __syncthreads();
+    const int wbase = th.w & ~(int)S.wmask;
+    typename T::Acc r = T::get(lds, wbase * lanes + lidx);
+    for (int j = 1; j < S.nwu; ++j) r = T::merge(r, T::get(lds, (wbase | (j << S.wlo)) * lanes + lidx), S.op);
+    a = r;
+  }
+  return a;
+}
+
+// Reduce the current output's block; returns segment P.gq's value (the output, or
+// this workgroup's partial of it when that segment spans workgroups).
+template <class T, int C, int NS, int U, int KD>
+__device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const typename T::Raw* __restrict__ in,
+                                                        long long base, bool vnone, const Thread<KD>& th, char* lds) {
+  using Acc = typename T::Acc;
+  constexpr int NO = NS > 1 ? NS - 1 : 1;
+  const int inner = P.nseg - 1;
+  const int stop = P.gq;
+  const int p = P.p, a_lv = P.a;
+  Acc outer[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) outer[j] = T::identity(j < P.nseg ? P.seg[j].op : 0);
+  int s[KD];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) s[k] = 0;
+  long long soff = 0;
+  Acc fin = T::identity(0);
+  // inner-segment levels with a single strip: a unit beyond the extent never loads
+  bool inner_ok = true;
+#pragma unroll
+  for (int m = 0; m < KD; ++m)
+    if (m >= a_lv && m < P.depth && P.lv[m].strips == 1 && P.lv[m].ragged) inner_ok = inner_ok && th.lim[m] > 0;
+  for (long long q = 0; q < P.outer_iters; ++q) {
+    bool vo = vnone && inner_ok;
+#pragma unroll
+    for (int m = 0; m < KD; ++m)
+      if (m >= p && m < a_lv && P.lv[m].ragged) vo = vo && (s[m] < th.lim[m]);
+    Acc ai = InnerStream<T, C, U, KD>::run(P, in, base + soff, vo, th);
+    ai = combine_seg<T, KD>(P, P.seg[inner], ai, th, lds);
+    if (inner == stop) {
+      fin = ai;
+    } else if constexpr (NS > 1) {
+      // feed the innermost segment's value to its parent, then finish the outer
+      // segments whose strips all end here
+#pragma unroll
+      for (int j = NO - 1; j >= 0; --j) {
+        if (j == inner - 1) {
+          const DevSeg& Sp = P.seg[j];
+          bool vj = true;
+          long long t = 0;
+#pragma unroll
+          for (int m = 0; m < KD; ++m) {
+            if (m >= Sp.first && m <= Sp.last && P.lv[m].ragged) vj = vj && (s[m] < th.lim[m]);
+            if (m == Sp.last) t = th.targ[m] + (long long)s[m] * P.lv[m].span;
+          }
+          if (vj) IntT::add(outer[j], IntT::emit(ai, P.seg[inner].op), t, Sp.op);
+        }
+      }
+      int J = 0;
+#pragma unroll
+      for (int m = 0; m < KD; ++m)
+        if (m >= p && m < a_lv && s[m] < P.lv[m].strips - 1) J = P.lv[m].seg + 1;
+#pragma unroll
+      for (int j = NO - 1; j >= 0; --j) {
+        if (j < inner && j >= J && j >= stop) {
+          const DevSeg& S = P.seg[j];
+          Acc v = combine_seg<T, KD>(P, S, outer[j], th, lds);
+          if (j > stop) {
+            const DevSeg& Sp = P.seg[j > 0 ? j - 1 : 0];
+            bool vj = true;
+            long long t = 0;
+#pragma unroll
+            for (int m = 0; m < KD; ++m) {
+              if (m >= Sp.first && m <= Sp.last && P.lv[m].ragged) vj = vj && (s[m] < th.lim[m]);
+              if (m == Sp.last) t = th.targ[m] + (long long)s[m] * P.lv[m].span;
+            }
+            if (vj) IntT::add(outer[j > 0 ? j - 1 : 0], IntT::emit(v, S.op), t, Sp.op);
+            outer[j] = T::identity(S.op);
+          } else {
+            outer[j] = v;
+          }
+        }
+      }
+    }
+    // advance the outer odometer (levels p .. a-1, innermost fastest)
+    bool carry = true;
+#pragma unroll
+    for (int m = KD - 1; m >= 0; --m) {
+      if (carry && m >= p && m < a_lv) {
+        ++s[m];
+        soff += P.lv[m].sstride;
+        if (s[m] == P.lv[m].strips) {
+          s[m] = 0;
+          soff -= P.lv[m].strips * P.lv[m].sstride;
+        } else {
+          carry = false;
+        }
+      }
+    }
+  }
+  Acc r = fin;
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+    if (j == stop && j != inner) r = outer[j];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// outputs and the grid combine
+
+__device__ __forceinline__ void store_int(const DevPlan& P, void* out, long long o, long long v) {
+  if (P.out_kind == OUT_I64) reinterpret_cast<long long*>(out)[o] = v;
+  else reinterpret_cast<int*>(out)[o] = (int)v;
+}
+__device__ __forceinline__ void store_flt(const DevPlan& P, void* out, long long o, double v) {
+  if (P.out_kind == OUT_F64) reinterpret_cast<double*>(out)[o] = v;
+  else reinterpret_cast<float*>(out)[o] = (float)v;
+}
+
+struct DPair {
+  double s, c;
+};
+__device__ __forceinline__ void dpair_add(DPair& a, double x) {
+  double s, e;
+  two_sum(a.s, x, s, e);
+  a.s = s;
+  a.c += e;
+}
+__device__ __forceinline__ DPair dpair_merge(DPair a, DPair b) {
+  double s, e;
+  two_sum(a.s, b.s, s, e);
+  const double c = (a.c + b.c) + e;
+  const double s2 = s + c;
+  return DPair{s2, c - (s2 - s)};
+}
+
+// The last workgroup to arrive folds the partials of one output.
+template <class T>
+struct GridFold;
+
+template <class R>
+struct GridFold<FloatT<R>> {
+  // fp64: each thread folds a strided subset, then a lane butterfly, then waves in order
+  template <int KD>
+  __device__ static double run(const DevPlan& P, const char* part, const Thread<KD>& th, char* lds) {
+    const int nthreads = P.nw * kWave;
+    const int tid = th.w * kWave + th.lane;
+    DPair a{0.0, 0.0};
+    for (long long k = tid; k < P.gsplit; k += nthreads) {
+      const FAcc v = FloatT<R>::get(part, k);
+      dpair_add(a, (double)v.s);
+      dpair_add(a, (double)v.c);
+    }
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const DPair o{xor_move_d(a.s, 1 << b, th.lane), xor_move_d(a.c, 1 << b, th.lane)};
+      a = dpair_merge(a, o);
+    }
+    __syncthreads();
+    double* slots = reinterpret_cast<double*>(lds);
+    if (th.lane == 0) {
+      slots[2 * th.w] = a.s;
+      slots[2 * th.w + 1] = a.c;
+    }
+    __syncthreads();
+    DPair r{slots[0], slots[1]};
+    for (int w = 1; w < P.nw; ++w) r = dpair_merge(r, DPair{slots[2 * w], slots[2 * w + 1]});
+    return r.s + r.c;
+  }
+};
+
+template <>
+struct GridFold<IntT> {
+  template <int KD>
+  __device__ static long long run(const DevPlan& P, const char* part, const Thread<KD>& th, char* lds) {
+    if (P.gmode == GCOMB_UNIFORM) {
+      const int op = P.seg[0].op;
+      const int nthreads = P.nw * kWave;
+      const int tid = th.w * kWave + th.lane;
+      IAcc a = IntT::identity(op);
+      for (long long k = tid; k < P.gsplit; k += nthreads) a = IntT::merge(a, IntT::get(part, k), op);
+#pragma unroll
+      for (int b = 0; b < 6; ++b) a = IntT::merge(a, IntT::shfl(a, 1 << b, th.lane), op);
+      __syncthreads();
+      if (th.lane == 0) IntT::put(lds, th.w, a);
+      __syncthreads();
+      IAcc r = IntT::get(lds, 0);
+      for (int w = 1; w < P.nw; ++w) r = IntT::merge(r, IntT::get(lds, w), op);
+      return IntT::emit(r, op);
+    }
+    // Several segments span workgroups.  Fold segment gq's partials, then apply the
+    // outer segments' operators in nest order.  Outer segments are pure grid levels
+    // with one iteration per workgroup, so their iteration index is the workgroup
+    // digit.  One thread, partials in index order.
+    long long* result = reinterpret_cast<long long*>(lds);
+    __syncthreads();
+    if (th.w == 0 && th.lane == 0) {
+      const int q = P.gq;
+      IAcc A[KD];
+      long long dg[KD];
+#pragma unroll
+      for (int j = 0; j < KD; ++j) {
+        A[j] = IntT::identity(j <= q ? P.seg[j].op : 0);
+        dg[j] = 0;
+      }
+      for (long long idx = 0; idx < P.gsplit; ++idx) {
+        const IAcc pv = IntT::get(part, idx);
+#pragma unroll
+        for (int j = 0; j < KD; ++j)
+          if (j == q) A[j] = IntT::merge(A[j], pv, P.seg[j].op);
+        bool carry = true;
+#pragma unroll
+        for (int j = KD - 1; j >= 0; --j) {
+          if (j <= q && carry) {
+            const DevSeg& S = P.seg[j];
+            if (dg[j] == (long long)S.gunits - 1) {
+              if (j > 0) {
+                const DevSeg& Sp = P.seg[j - 1];
+                long long rem = dg[j - 1];
+                bool valid = true;
+                long long t_last = 0;
+                for (int l = Sp.last; l >= Sp.first; --l) {
+                  const long long gfl = P.lv[l].gf;
+                  const long long t = rem % gfl;
+                  rem /= gfl;
+                  if (t >= P.lv[l].e) valid = false;
+                  if (l == Sp.last) t_last = t;
+                }
+                if (valid) IntT::add(A[j - 1], IntT::emit(A[j], S.op), t_last, Sp.op);
+                A[j] = IntT::identity(S.op);
+              }
+              dg[j] = 0;
+            } else {
+              dg[j] += 1;
+              carry = false;
+            }
+          }
+        }
+      }
+      *result = IntT::emit(A[0], P.seg[0].op);
+    }
+    __syncthreads();
+    return *result;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// one workgroup
+
+template <class T, int C, int NS, int U, int KD>
+__device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* __restrict__ in,
+                                       void* __restrict__ out, unsigned char* __restrict__ ws, uint32_t g,
+                                       char* lds) {
+  Thread<KD> th;
+  th.w = (int)(threadIdx.x >> 6);
+  th.lane = (int)(threadIdx.x & 63);
+  long long base_none = 0, base_o = 0, base_red = 0;
+#pragma unroll
+  for (int m = 0; m < KD; ++m) {
+    th.lim[m] = 1;
+    th.targ[m] = 0;
+    if (m < P.depth) {
+      const DevLevel& L = P.lv[m];
+      const uint32_t ug = (g / L.gdiv) % L.gf;
+      const uint32_t uw = ((uint32_t)th.w >> L.wsh) & (uint32_t)(L.wf - 1);
+      const uint32_t uv = ((uint32_t)th.lane >> L.vsh) & (uint32_t)(L.vf - 1);
+      const long long t0 = (long long)(((unsigned long long)ug * L.wf + uw) * L.vf + uv) * L.chunk;
+      th.lim[m] = t0 < L.e ? (int)((L.e - t0 + L.span - 1) / L.span) : 0;
+      th.targ[m] = (int)t0;
+      if (m < P.p) {
+        base_none += t0 * L.stride;
+        base_o += t0 * L.ostride;
+      } else {
+        base_red += t0 * L.stride;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KD; ++k) {
+    th.limc[k] = 1;
+#pragma unroll
+    for (int m = 0; m < KD; ++m)
+      if (k < P.nid && m == P.id_level[k]) th.limc[k] = th.lim[m];
+  }
+  const bool red_writer = ((th.lane & (int)(P.red_vmask | P.idle_vmask)) == 0) &&
+                          ((th.w & (int)(P.red_wmask | P.idle_wmask)) == 0);
+  const uint32_t gred = (uint32_t)((unsigned long long)g % (unsigned long long)P.gsplit);
+  int* flag = reinterpret_cast<int*>(lds);
+
+  int sn[KD];
+#pragma unroll
+  for (int m = 0; m < KD; ++m) sn[m] = 0;
+  long long noff = 0, nout = 0;
+  for (long long q = 0; q < P.none_iters; ++q) {
+    bool vnone = true;
+#pragma unroll
+    for (int m = 0; m < KD; ++m)
+      if (m < P.p && P.lv[m].ragged) vnone = vnone && (sn[m] < th.lim[m]);
+    const long long off = base_none + noff;
+    const long long o = base_o + nout;
+    if (P.p == P.depth) {  // nothing reduces: a copy
+      if (vnone && red_writer) {
+        if constexpr (T::kFloat) {
+          double v;
+          if constexpr (sizeof(typename T::Raw) == 2) v = (double)bf16_lo(in[off]);
+          else v = (double)in[off];
+          store_flt(P, out, o, v);
+        } else {
+          store_int(P, out, o, (long long)in[off]);
+        }
+      }
+    } else {
+      const typename T::Acc a = reduce_block<T, C, NS, U, KD>(P, in, off + base_red, vnone, th, lds);
+      if (P.gmode == GCOMB_NONE) {
+        if (vnone && red_writer) {
+          if constexpr (T::kFloat) store_flt(P, out, o, (double)a.s + (double)a.c);
+          else store_int(P, out, o, IntT::emit(a, P.seg[0].op));
+        }
+      } else if (vnone) {  // uniform here: with a grid combine every NONE level is on G only
+        // grid combine: publish this workgroup's partial, then take a ticket
+        char* part = reinterpret_cast<char*>(ws) + o * P.gsplit * kSlotBytes;
+        unsigned int* tickets =
+            reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(ws) + P.n_out * P.gsplit * kSlotBytes);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          T::put(part, gred, a);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          const unsigned int old =
+              __hip_atomic_fetch_add(&tickets[o], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          *flag = (old == (unsigned int)(P.gsplit - 1)) ? 1 : 0;
+        }
+        __syncthreads();
+        const bool last = *flag != 0;
+        __syncthreads();
+        if (last) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          const auto v = GridFold<T>::template run<KD>(P, part, th, lds);
+          if (threadIdx.x == 0) {
+            if constexpr (T::kFloat) store_flt(P, out, o, v);
+            else store_int(P, out, o, v);
+            __hip_atomic_store(&tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // advance the NONE odometer
+    bool carry = true;
+#pragma unroll
+    for (int m = KD - 1; m >= 0; --m) {
+      if (carry && m < P.p) {
+        ++sn[m];
+        noff += P.lv[m].sstride;
+        nout += P.lv[m].span * P.lv[m].ostride;
+        if (sn[m] == P.lv[m].strips) {
+          sn[m] = 0;
+          noff -= P.lv[m].strips * P.lv[m].sstride;
+          nout -= P.lv[m].strips * P.lv[m].span * P.lv[m].ostride;
+        } else {
+          carry = false;
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t logical_group(const DevPlan& P, uint32_t b) {
+  if (!P.xcd) return b;
+  const uint32_t per = (uint32_t)P.grid >> 3;  // grid % 8 == 0 when xcd is set
+  return (b & 7u) * per + (b >> 3);
+}
+
+// Launchers, one per input type (each in its own translation unit).  P is the host
+// copy (launch geometry), dP the same plan in device memory (read by the kernel).
+hp_status launch_nest_f32(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
+                          hipStream_t st);
+hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
+                           hipStream_t st);
+hp_status launch_nest_i32(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
+                          hipStream_t st);
+
+}  // namespace hp

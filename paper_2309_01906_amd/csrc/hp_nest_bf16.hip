@@ -1,0 +1,30 @@
+// Nest kernels for bf16 inputs (SUM levels, exact widening to fp32, fp32 pair accumulation, fp64 output).
+#include "hp_nest.h"
+
+namespace hp {
+
+template <int C, int KD>
+__global__ void __launch_bounds__(1024) k_nest_bf16(const DevPlan* __restrict__ Pd, const uint16_t* __restrict__ in,
+                                                   void* __restrict__ out, unsigned char* __restrict__ ws) {
+  extern __shared__ __align__(16) char lds[];
+  const DevPlan& P = *Pd;
+  wg_run<FloatT<uint16_t>, C, 1, (C == 1 ? 16 : 8), KD>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+}
+
+hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {
+  const dim3 grid((unsigned int)P.grid), block((unsigned int)(P.nw * kWave));
+  const uint16_t* x = reinterpret_cast<const uint16_t*>(in);
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  if (P.depth <= 4) {
+    if (P.chunk == 8) hipLaunchKernelGGL((k_nest_bf16<8, 4>), grid, block, lds, st, dP, x, out, w);
+    else hipLaunchKernelGGL((k_nest_bf16<1, 4>), grid, block, lds, st, dP, x, out, w);
+  } else {
+    if (P.chunk == 8) hipLaunchKernelGGL((k_nest_bf16<8, kMaxDepth>), grid, block, lds, st, dP, x, out, w);
+    else hipLaunchKernelGGL((k_nest_bf16<1, kMaxDepth>), grid, block, lds, st, dP, x, out, w);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+}  // namespace hp

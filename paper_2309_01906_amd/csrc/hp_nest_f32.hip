@@ -1,0 +1,30 @@
+// Nest kernels for fp32 inputs (SUM levels, fp32 pair accumulation, fp64 output).
+#include "hp_nest.h"
+
+namespace hp {
+
+template <int C, int KD>
+__global__ void __launch_bounds__(1024) k_nest_f32(const DevPlan* __restrict__ Pd, const float* __restrict__ in,
+                                                   void* __restrict__ out, unsigned char* __restrict__ ws) {
+  extern __shared__ __align__(16) char lds[];
+  const DevPlan& P = *Pd;
+  wg_run<FloatT<float>, C, 1, (C == 1 ? 16 : 8), KD>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+}
+
+hp_status launch_nest_f32(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {
+  const dim3 grid((unsigned int)P.grid), block((unsigned int)(P.nw * kWave));
+  const float* x = reinterpret_cast<const float*>(in);
+  unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+  if (P.depth <= 4) {
+    if (P.chunk == 4) hipLaunchKernelGGL((k_nest_f32<4, 4>), grid, block, lds, st, dP, x, out, w);
+    else hipLaunchKernelGGL((k_nest_f32<1, 4>), grid, block, lds, st, dP, x, out, w);
+  } else {
+    if (P.chunk == 4) hipLaunchKernelGGL((k_nest_f32<4, kMaxDepth>), grid, block, lds, st, dP, x, out, w);
+    else hipLaunchKernelGGL((k_nest_f32<1, kMaxDepth>), grid, block, lds, st, dP, x, out, w);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+}  // namespace hp

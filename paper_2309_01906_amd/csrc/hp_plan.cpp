@@ -1,0 +1,504 @@
+// Level-mapping planner (host only; no HIP calls, so it also runs without a GPU).
+//
+// Follows the paper's section 3: explicit level selection with collapse (3.1),
+// selection by property for the automatic map (3.2: reductions need a shuffle at
+// the wavefront, a barrier and local memory at the workgroup, and an atomic at the
+// grid, which has no barrier), the reserve rule that makes maps monotone (3.3),
+// strip-mining every level once all units are started (3.4, SPMD mode), static /
+// masked schedules (3.5) and splitting a hardware level between nested loops (3.8).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "hp_internal.h"
+
+namespace hp {
+
+static thread_local char g_err[512];
+
+hp_status fail(hp_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+static inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+static inline uint64_t pow2ceil(uint64_t x) {
+  uint64_t r = 1;
+  while (r < x) r <<= 1;
+  return r;
+}
+static inline int log2u(uint64_t x) {
+  int r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int lowbit(uint32_t s) { return __builtin_ctz(s); }
+static inline int highbit(uint32_t s) { return 31 - __builtin_clz(s); }
+// Every level is strip-mined once its units are exhausted, so an L bit next to
+// other scopes only states that strips are expected; for the nesting order it is
+// the other scopes that count.  A level on L alone is serial in one lane.
+static inline int nest_high(uint32_t s) { return s == HP_SCOPE_L ? highbit(s) : highbit(s & ~(uint32_t)HP_SCOPE_L); }
+
+static int elem_bytes(int dt) { return dt == HP_BF16 ? 2 : 4; }
+
+// Automatic map: NONE levels on the grid; reducing levels fill the lanes of a
+// wavefront from the innermost level outward (shuffles are the cheapest combine),
+// then the waves of a workgroup (LDS + barrier), then, when the outputs alone do
+// not give the chip enough workgroups, the outermost reducing level is also split
+// over the grid (atomic ticket combine).
+static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m) {
+  const int d = n->depth;
+  memset(m, 0, sizeof *m);
+  for (int l = 0; l < p; ++l) m->scopes[l] = HP_SCOPE_G;
+  if (p == d) return;
+  // lanes of one wavefront, innermost reducing level first
+  int lanes_left = kWave;
+  int l = d - 1;
+  int first_v = d;
+  while (l >= p && lanes_left > 1) {
+    const int64_t need = cdiv(n->extent[l], l == d - 1 ? chunk_last : 1);
+    uint64_t f = pow2ceil((uint64_t)need);
+    if (f >= (uint64_t)lanes_left || l == p) f = (uint64_t)lanes_left;
+    m->scopes[l] = HP_SCOPE_V;
+    m->units[l][HP_AXIS_V] = (uint32_t)f;
+    lanes_left /= (int)f;
+    first_v = l;
+    --l;
+  }
+  if (lanes_left > 1) m->units[first_v][HP_AXIS_V] *= (uint32_t)lanes_left;
+  int64_t block = 1;
+  for (int k = p; k < d; ++k) block *= n->extent[k];
+  const int64_t bytes = block * elem_bytes(n->dtype);
+  const uint64_t nw_target = bytes >= (256 << 10) ? 8 : bytes >= (16 << 10) ? 4 : bytes >= (4 << 10) ? 2 : 1;
+  // waves of one workgroup: the next level outward, or the outermost lane level
+  int w_level;
+  int64_t per_wave_unit;
+  if (l >= p) {
+    w_level = l;
+    m->scopes[l] = HP_SCOPE_W;
+    per_wave_unit = n->extent[l];
+    --l;
+  } else {
+    w_level = first_v;
+    m->scopes[first_v] |= HP_SCOPE_W;
+    per_wave_unit = cdiv(cdiv(n->extent[first_v], first_v == d - 1 ? chunk_last : 1),
+                         m->units[first_v][HP_AXIS_V]);
+  }
+  {
+    uint64_t f = pow2ceil((uint64_t)per_wave_unit);
+    if (f > nw_target) f = nw_target;
+    m->units[w_level][HP_AXIS_W] = (uint32_t)f;
+  }
+  // anything further out runs on the grid, one workgroup per iteration
+  for (int k = p; k <= l; ++k) m->scopes[k] = HP_SCOPE_G;
+  // too few outputs for the chip: split the outermost reducing level over the grid
+  if (l < p) {
+    int64_t n_out = 1;
+    for (int k = 0; k < p; ++k) n_out *= n->extent[k];
+    const int64_t target_wgs = 2048;
+    if (n_out < target_wgs) {
+      const int64_t per = p == d - 1 ? cdiv(n->extent[p], chunk_last) : n->extent[p];
+      const int64_t in_wg = (int64_t)(m->units[p][HP_AXIS_V] ? m->units[p][HP_AXIS_V] : 1) *
+                            (int64_t)(m->units[p][HP_AXIS_W] ? m->units[p][HP_AXIS_W] : 1);
+      int64_t gf = cdiv(target_wgs, n_out);
+      const int64_t useful = cdiv(per, in_wg);
+      const int64_t by_bytes = bytes / (64 << 10);  // keep >= 64 KiB of input per workgroup
+      if (gf > useful) gf = useful;
+      if (gf > by_bytes) gf = by_bytes;
+      if (gf > 1) {
+        m->scopes[p] |= HP_SCOPE_G;
+        m->units[p][HP_AXIS_G] = (uint32_t)gf;
+      }
+    }
+  }
+}
+
+hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out) {
+  if (!n || !out) return fail(HP_EINVAL, "null argument");
+  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_TEMPORAL))
+    return fail(HP_EINVAL, "unknown flag bits 0x%x", flags);
+  const int d = n->depth;
+  if (d < 1 || d > kMaxDepth) return fail(HP_EINVAL, "depth %d outside [1, %d]", d, kMaxDepth);
+  if (n->dtype != HP_I32 && n->dtype != HP_F32 && n->dtype != HP_BF16)
+    return fail(HP_EINVAL, "input dtype %d is not I32, F32 or BF16", n->dtype);
+  const bool is_float = n->dtype != HP_I32;
+  int p = d;
+  int64_t total = 1;
+  for (int l = 0; l < d; ++l) {
+    const int64_t e = n->extent[l];
+    const int op = n->op[l];
+    if (e < 1) return fail(HP_EINVAL, "extent[%d] = %lld < 1", l, (long long)e);
+    if (op < HP_OP_NONE || op > HP_OP_ARGMAX) return fail(HP_EINVAL, "op[%d] = %d unknown", l, op);
+    if (op == HP_OP_NONE && p != d) return fail(HP_EINVAL, "NONE at level %d after a reducing level", l);
+    if (op != HP_OP_NONE && p == d) p = l;
+    if (is_float && op != HP_OP_NONE && op != HP_OP_SUM)
+      return fail(HP_EUNSUPPORTED, "float inputs support SUM only (level %d)", l);
+    if ((op == HP_OP_ARGMIN || op == HP_OP_ARGMAX) && e > 2147483647LL)
+      return fail(HP_EUNSUPPORTED, "ARG level %d longer than 2^31-1", l);
+    if (total > (int64_t(1) << 62) / e) return fail(HP_EUNSUPPORTED, "nest has more than 2^62 elements");
+    total *= e;
+  }
+  // innermost chunk: as many elements as one 16-byte load holds, if the extent allows
+  int chunk_last = 1;
+  if (p < d && !(flags & HP_FLAG_SCALAR)) {
+    // the kernels are built for a full 16-byte chunk or single elements
+    const int c = 16 / elem_bytes(n->dtype);
+    chunk_last = (n->extent[d - 1] % c == 0) ? c : 1;
+  }
+
+  hp_level_map m;
+  if (map_in) {
+    m = *map_in;
+  } else {
+    auto_map(n, p, chunk_last, &m);
+  }
+  // ---- validate the map
+  for (int l = 0; l < d; ++l) {
+    const uint32_t s = m.scopes[l];
+    if (s == 0 || (s & ~0xFu)) return fail(HP_EINVAL, "scopes[%d] = 0x%x is not a non-empty scope set", l, s);
+    const uint32_t run = s >> lowbit(s);
+    if (run & (run + 1)) return fail(HP_EINVAL, "scopes[%d] = 0x%x is not a run of adjacent scopes", l, s);
+    for (int a = 0; a < 3; ++a) {
+      if (m.units[l][a] && !(s & (1u << a)))
+        return fail(HP_EINVAL, "units[%d][%d] set for a scope the level does not use", l, a);
+    }
+    if (m.units[l][HP_AXIS_W] && (!is_pow2(m.units[l][HP_AXIS_W]) || m.units[l][HP_AXIS_W] > kMaxWaves))
+      return fail(HP_EINVAL, "W units of level %d must be a power of two <= %d", l, kMaxWaves);
+    if (m.units[l][HP_AXIS_V] && (!is_pow2(m.units[l][HP_AXIS_V]) || m.units[l][HP_AXIS_V] > kWave))
+      return fail(HP_EINVAL, "V units of level %d must be a power of two <= %d", l, kWave);
+  }
+  for (int l = 0; l < d; ++l)
+    for (int k = 0; k < l; ++k)
+      if (lowbit(m.scopes[l]) < nest_high(m.scopes[k]))
+        return fail(HP_EINVAL, "map not monotone: level %d uses a scope outer to level %d's", l, k);
+
+  DevPlan dp;
+  memset(&dp, 0, sizeof dp);
+  dp.depth = d;
+  dp.p = p;
+  dp.dtype = n->dtype;
+  dp.flags = (int32_t)flags;
+  dp.in_elems = total;
+  for (int l = 0; l < d; ++l) {
+    DevLevel& L = dp.lv[l];
+    L.e = n->extent[l];
+    L.op = n->op[l];
+    L.chunk = (l == d - 1) ? chunk_last : 1;
+    L.gf = 1;
+    L.wf = 1;
+    L.vf = 1;
+    L.seg = -1;
+  }
+  dp.lv[d - 1].stride = 1;
+  for (int l = d - 2; l >= 0; --l) dp.lv[l].stride = dp.lv[l + 1].stride * dp.lv[l + 1].e;
+  dp.chunk = chunk_last;
+
+  // ---- V axis: 64 lanes split between the levels that use it (outer = high bits)
+  {
+    uint64_t fixed = 1;
+    int n_auto = 0, outer_auto = -1;
+    for (int l = 0; l < d; ++l)
+      if (m.scopes[l] & HP_SCOPE_V) {
+        if (m.units[l][HP_AXIS_V]) fixed *= m.units[l][HP_AXIS_V];
+        else {
+          ++n_auto;
+          if (outer_auto < 0) outer_auto = l;
+        }
+      }
+    if (fixed > (uint64_t)kWave) return fail(HP_EINVAL, "V units multiply to %llu > 64", (unsigned long long)fixed);
+    uint64_t left = kWave / fixed;
+    for (int l = d - 1; l >= 0; --l) {
+      if (!(m.scopes[l] & HP_SCOPE_V)) continue;
+      uint64_t f = m.units[l][HP_AXIS_V];
+      if (!f) {
+        if (l == outer_auto) f = left;
+        else {
+          f = pow2ceil((uint64_t)cdiv(dp.lv[l].e, dp.lv[l].chunk));
+          if (f > left) f = left;
+        }
+        left /= f;
+      }
+      dp.lv[l].vf = (int32_t)f;
+    }
+    int sh = 0;
+    for (int l = d - 1; l >= 0; --l)
+      if (m.scopes[l] & HP_SCOPE_V) {
+        dp.lv[l].vsh = sh;
+        sh += log2u(dp.lv[l].vf);
+      }
+    dp.idle_vmask = (sh >= 6) ? 0u : (0xFFFFFFFFu << sh) & 0x3Fu;
+  }
+  // ---- W axis: waves per workgroup
+  {
+    uint64_t fixed = 1;
+    for (int l = 0; l < d; ++l)
+      if ((m.scopes[l] & HP_SCOPE_W) && m.units[l][HP_AXIS_W]) fixed *= m.units[l][HP_AXIS_W];
+    if (fixed > (uint64_t)kMaxWaves)
+      return fail(HP_EINVAL, "W units multiply to %llu > %d", (unsigned long long)fixed, kMaxWaves);
+    uint64_t left = 4 / (fixed < 4 ? fixed : 4);  // default budget for levels left to the planner
+    if (left < 1) left = 1;
+    for (int l = d - 1; l >= 0; --l) {
+      if (!(m.scopes[l] & HP_SCOPE_W)) continue;
+      uint64_t f = m.units[l][HP_AXIS_W];
+      if (!f) {
+        int64_t per = cdiv(dp.lv[l].e, (int64_t)dp.lv[l].chunk * dp.lv[l].vf);
+        f = pow2ceil((uint64_t)per);
+        if (f > left) f = left;
+        left /= f;
+        if (left < 1) left = 1;
+      }
+      dp.lv[l].wf = (int32_t)f;
+    }
+    int sh = 0;
+    for (int l = d - 1; l >= 0; --l)
+      if (m.scopes[l] & HP_SCOPE_W) {
+        dp.lv[l].wsh = sh;
+        sh += log2u(dp.lv[l].wf);
+      }
+    dp.nw = 1 << sh;
+    if (dp.nw > kMaxWaves) return fail(HP_EINVAL, "more than %d waves per workgroup", kMaxWaves);
+    dp.idle_wmask = 0;
+  }
+  // ---- segments of reducing levels
+  dp.nseg = 0;
+  for (int l = p; l < d; ++l) {
+    const int op = dp.lv[l].op;
+    const bool arg = op == HP_OP_ARGMIN || op == HP_OP_ARGMAX;
+    const bool joins = l > p && dp.lv[l - 1].op == op && !arg;
+    if (!joins) {
+      DevSeg& S = dp.seg[dp.nseg];
+      memset(&S, 0, sizeof S);
+      S.first = l;
+      S.op = op;
+      ++dp.nseg;
+    }
+    dp.seg[dp.nseg - 1].last = l;
+    dp.lv[l].seg = dp.nseg - 1;
+  }
+  // ---- G axis
+  {
+    // which segment is the innermost one with grid units (requested or planned)
+    int gq = -1;
+    for (int l = p; l < d; ++l)
+      if ((m.scopes[l] & HP_SCOPE_G) && (m.units[l][HP_AXIS_G] != 1)) gq = dp.lv[l].seg;
+    for (int l = 0; l < d; ++l) {
+      if (!(m.scopes[l] & HP_SCOPE_G)) continue;
+      uint64_t f = m.units[l][HP_AXIS_G];
+      DevLevel& L = dp.lv[l];
+      const int64_t inner_units = (int64_t)L.wf * L.vf * L.chunk;
+      if (l < p) {
+        if (!f) f = (uint64_t)cdiv(L.e, inner_units);
+      } else if (L.seg < gq) {
+        // reducing level outside the innermost grid-spanning segment: it must
+        // finish on the grid in one strip, so that its operator is applied after
+        // the cross-workgroup combine of the segment inside it
+        const uint64_t need = (uint64_t)cdiv(L.e, inner_units);
+        if (!f) f = need;
+        if (f < need)
+          return fail(HP_EUNSUPPORTED,
+                      "level %d reduces outside a grid-spanning segment and needs >= %llu grid units",
+                      l, (unsigned long long)need);
+      } else {
+        if (!f) {
+          // planner's choice for an explicit G scope without units: fill the machine
+          int64_t outs = 1;
+          for (int k = 0; k < p; ++k) outs *= dp.lv[k].e;
+          int64_t want = cdiv(2048, outs);
+          int64_t useful = cdiv(L.e, inner_units);
+          f = (uint64_t)(want < useful ? want : useful);
+          if (f < 1) f = 1;
+        }
+      }
+      if (f > 0x7FFFFFFFull) return fail(HP_EUNSUPPORTED, "level %d asks for more than 2^31 workgroups", l);
+      L.gf = (uint32_t)f;
+    }
+    // reducing grid product
+    uint64_t gs = 1;
+    for (int l = p; l < d; ++l) {
+      gs *= dp.lv[l].gf;
+      if (gs > (1ull << 24)) return fail(HP_EUNSUPPORTED, "more than 2^24 workgroups per output");
+    }
+    dp.gsplit = (int64_t)gs;
+    // cap the grid: NONE levels give up units (and take strips) from the outermost inward
+    const uint64_t block_threads = (uint64_t)dp.nw * kWave;
+    const uint64_t max_grid = ((1ull << 31) / block_threads);
+    uint64_t grid = gs;
+    for (int l = 0; l < p; ++l) grid *= dp.lv[l].gf;
+    for (int l = 0; l < p && grid > max_grid; ++l) {
+      if (!(m.scopes[l] & HP_SCOPE_G) || m.units[l][HP_AXIS_G]) continue;
+      uint64_t others = grid / dp.lv[l].gf;
+      uint64_t f = max_grid / others;
+      if (f < 1) f = 1;
+      dp.lv[l].gf = (uint32_t)f;
+      grid = others * f;
+    }
+    if (grid > max_grid) return fail(HP_EUNSUPPORTED, "grid of %llu workgroups exceeds the launch limit",
+                                     (unsigned long long)grid);
+    dp.grid = (int64_t)grid;
+    uint64_t div = 1;
+    for (int l = d - 1; l >= 0; --l) {
+      dp.lv[l].gdiv = (uint32_t)div;
+      div *= dp.lv[l].gf;
+    }
+  }
+  // ---- per-level strips
+  dp.none_iters = 1;
+  dp.red_iters = 1;
+  for (int l = 0; l < d; ++l) {
+    DevLevel& L = dp.lv[l];
+    L.span = (int64_t)L.gf * L.wf * L.vf * L.chunk;
+    L.strips = cdiv(L.e, L.span);
+    L.sstride = L.span * L.stride;
+    L.ragged = (L.strips * L.span != L.e) ? 1 : 0;
+    if (l < p) dp.none_iters *= L.strips;
+    else dp.red_iters *= L.strips;
+  }
+  {
+    int64_t os = 1;
+    for (int l = p - 1; l >= 0; --l) {
+      dp.lv[l].ostride = os;
+      os *= dp.lv[l].e;
+    }
+    dp.n_out = os;
+  }
+  // ---- segment masks and the grid-combine mode
+  dp.red_vmask = dp.red_wmask = 0;
+  uint32_t outer_v = 0;
+  for (int l = 0; l < p; ++l) outer_v |= (uint32_t)(dp.lv[l].vf - 1) << dp.lv[l].vsh;
+  dp.lds_slot_lanes = 1;
+  int gq = -1;
+  for (int j = 0; j < dp.nseg; ++j) {
+    DevSeg& S = dp.seg[j];
+    S.vmask = S.wmask = 0;
+    S.gunits = 1;
+    S.wlo = 31;
+    for (int l = S.first; l <= S.last; ++l) {
+      const DevLevel& L = dp.lv[l];
+      S.vmask |= (uint32_t)(L.vf - 1) << L.vsh;
+      S.wmask |= (uint32_t)(L.wf - 1) << L.wsh;
+      if (L.wf > 1 && L.wsh < S.wlo) S.wlo = L.wsh;
+      S.gunits *= L.gf;
+    }
+    if (S.wlo == 31) S.wlo = 0;
+    S.nwu = 1 << __builtin_popcount(S.wmask);
+    S.lds_lanes = outer_v;
+    if (S.wmask && outer_v) dp.lds_slot_lanes = kWave;
+    outer_v |= S.vmask;
+    dp.red_vmask |= S.vmask;
+    dp.red_wmask |= S.wmask;
+    if (S.gunits > 1) gq = j;
+  }
+  if (gq < 0) {
+    dp.gmode = GCOMB_NONE;
+    dp.gsplit = 1;
+  } else {
+    // every reducing level before segment gq must finish in one strip (enforced above for
+    // explicit units; also true for planner-chosen ones)
+    for (int l = p; l < dp.seg[gq].first; ++l)
+      if (dp.lv[l].strips != 1)
+        return fail(HP_EUNSUPPORTED, "level %d must complete in one strip on the grid", l);
+    dp.gmode = gq == 0 ? GCOMB_UNIFORM : GCOMB_NESTED;
+  }
+  dp.gq = gq < 0 ? 0 : gq;
+  // innermost-segment stream description
+  dp.a = dp.nseg > 0 ? dp.seg[dp.nseg - 1].first : d;
+  dp.nid = 0;
+  dp.inner_iters = 1;
+  dp.outer_iters = 1;
+  dp.last_dim_is_last_level = 0;
+  for (int l = p; l < d; ++l) {
+    if (l < dp.a) {
+      dp.outer_iters *= dp.lv[l].strips;
+    } else {
+      dp.inner_iters *= dp.lv[l].strips;
+      if (dp.lv[l].strips > 1) {
+        dp.id_strips[dp.nid] = dp.lv[l].strips;
+        dp.id_sstride[dp.nid] = dp.lv[l].sstride;
+        dp.id_level[dp.nid] = l;
+        dp.id_ragged[dp.nid] = dp.lv[l].ragged;
+        if (l == d - 1) dp.last_dim_is_last_level = 1;
+        ++dp.nid;
+      }
+    }
+  }
+  for (int l = 0; l < d; ++l)
+    if (dp.lv[l].strips > 0x7FFFFFFFll)
+      return fail(HP_EUNSUPPORTED, "level %d needs more than 2^31 strips; give it more units", l);
+  dp.xcd = (!(flags & HP_FLAG_NO_XCD) && dp.grid % 8 == 0 && dp.grid >= 16) ? 1 : 0;
+  // ---- output kind
+  if (is_float) {
+    dp.out_kind = (flags & HP_FLAG_OUT_F32) ? OUT_F32 : OUT_F64;
+  } else {
+    dp.out_kind = OUT_I32;
+    for (int l = p; l < d; ++l) {
+      if (dp.lv[l].op == HP_OP_SUM) { dp.out_kind = OUT_I64; break; }
+      if (dp.lv[l].op == HP_OP_ARGMIN || dp.lv[l].op == HP_OP_ARGMAX) { dp.out_kind = OUT_I32; break; }
+    }
+  }
+  // ---- info
+  hp_plan_info& I = out->info;
+  memset(&I, 0, sizeof I);
+  I.depth = d;
+  I.out_dtype = dp.out_kind;
+  I.n_out = dp.n_out;
+  const size_t osz = (dp.out_kind == OUT_I32 || dp.out_kind == OUT_F32) ? 4 : 8;
+  I.out_bytes = (size_t)dp.n_out * osz;
+  I.in_elems = total;
+  I.in_bytes = (size_t)total * elem_bytes(n->dtype);
+  I.grid = dp.grid;
+  I.waves = dp.nw;
+  I.chunk = chunk_last;
+  I.gsplit = dp.gsplit;
+  I.workspace_bytes = dp.gsplit > 1 ? (size_t)dp.n_out * dp.gsplit * kSlotBytes + (size_t)dp.n_out * 4 + 256 : 0;
+  {
+    size_t slots = (size_t)dp.nw * dp.lds_slot_lanes * kSlotBytes;
+    size_t gcomb = (size_t)dp.nw * 32;
+    I.lds_bytes = (slots > gcomb ? slots : gcomb) + 16;
+  }
+  for (int l = 0; l < d; ++l) {
+    I.scopes[l] = m.scopes[l];
+    I.units[l][HP_AXIS_G] = dp.lv[l].gf;
+    I.units[l][HP_AXIS_W] = (uint32_t)dp.lv[l].wf;
+    I.units[l][HP_AXIS_V] = (uint32_t)dp.lv[l].vf;
+    I.strips[l] = dp.lv[l].strips;
+  }
+  I.nseg = dp.nseg;
+  out->dp = dp;
+  return HP_OK;
+}
+
+}  // namespace hp
+
+extern "C" const char* hp_last_error(void) { return hp::g_err; }
+
+extern "C" const char* hp_status_str(hp_status s) {
+  switch (s) {
+    case HP_OK: return "HP_OK";
+    case HP_EINVAL: return "HP_EINVAL";
+    case HP_EUNSUPPORTED: return "HP_EUNSUPPORTED";
+    case HP_ENOMEM: return "HP_ENOMEM";
+    case HP_EDEVICE: return "HP_EDEVICE";
+    case HP_EAGAIN: return "HP_EAGAIN";
+    case HP_ETOOBIG: return "HP_ETOOBIG";
+    case HP_ENOTREADY: return "HP_ENOTREADY";
+    case HP_ECANCELED: return "HP_ECANCELED";
+    case HP_ESTATE: return "HP_ESTATE";
+  }
+  return "unknown status";
+}
+
+extern "C" hp_status hp_plan_inspect(const hp_nest* nest, const hp_level_map* map, uint32_t flags,
+                                     hp_plan_info* info) {
+  if (!info) return hp::fail(HP_EINVAL, "null info");
+  hp::Lowered L;
+  hp_status s = hp::lower(nest, map, flags, &L);
+  if (s != HP_OK) return s;
+  *info = L.info;
+  return HP_OK;
+}

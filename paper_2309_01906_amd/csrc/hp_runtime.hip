@@ -1,0 +1,91 @@
+// Plan objects and the single-nest entry points of the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <new>
+
+#include "hp_internal.h"
+
+#include "hp_nest.h"
+
+struct hp_plan_s {
+  hp::DevPlan dp;        // host copy: launch geometry
+  hp::DevPlan* d_dp;     // device copy: read by the kernels
+  hp_plan_info info;
+  void* ws;
+  int device;
+};
+
+extern "C" hp_status hp_plan(const hp_nest* nest, const hp_level_map* map, uint32_t flags, hp_plan_t* out) {
+  if (!out) return hp::fail(HP_EINVAL, "null output handle");
+  *out = nullptr;
+  hp::Lowered L;
+  hp_status s = hp::lower(nest, map, flags, &L);
+  if (s != HP_OK) return s;
+  hp_plan_s* p = new (std::nothrow) hp_plan_s;
+  if (!p) return hp::fail(HP_ENOMEM, "host allocation of the plan failed");
+  p->dp = L.dp;
+  p->info = L.info;
+  p->ws = nullptr;
+  p->d_dp = nullptr;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return hp::fail(HP_EDEVICE, "no HIP device");
+  }
+  if (hipMalloc(&p->d_dp, sizeof(hp::DevPlan)) != hipSuccess) {
+    delete p;
+    return hp::fail(HP_ENOMEM, "device plan allocation failed");
+  }
+  if (hipMemcpy(p->d_dp, &p->dp, sizeof(hp::DevPlan), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->d_dp);
+    delete p;
+    return hp::fail(HP_EDEVICE, "device plan upload failed");
+  }
+  if (p->info.workspace_bytes) {
+    if (hipMalloc(&p->ws, p->info.workspace_bytes) != hipSuccess) {
+      (void)hipFree(p->d_dp);
+      delete p;
+      return hp::fail(HP_ENOMEM, "workspace allocation of %zu bytes failed", L.info.workspace_bytes);
+    }
+    // partials need no clearing; tickets start at zero and every run leaves them at zero
+    if (hipMemset(p->ws, 0, p->info.workspace_bytes) != hipSuccess) {
+      (void)hipFree(p->ws);
+      (void)hipFree(p->d_dp);
+      delete p;
+      return hp::fail(HP_EDEVICE, "workspace clear failed");
+    }
+  }
+  *out = p;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_plan_info_get(hp_plan_t plan, hp_plan_info* info) {
+  if (!plan || !info) return hp::fail(HP_EINVAL, "null argument");
+  *info = plan->info;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_run(hp_plan_t plan, const void* d_in, void* d_out, void* stream) {
+  if (!plan) return hp::fail(HP_EINVAL, "null plan");
+  if (!d_in || !d_out) return hp::fail(HP_EINVAL, "null input or output pointer");
+  if (reinterpret_cast<uintptr_t>(d_in) & 15u) return hp::fail(HP_EINVAL, "input not 16-byte aligned");
+  const uintptr_t oal = (plan->info.out_dtype == HP_I64 || plan->info.out_dtype == HP_F64) ? 7u : 3u;
+  if (reinterpret_cast<uintptr_t>(d_out) & oal) return hp::fail(HP_EINVAL, "output misaligned for its type");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+    return hp::fail(HP_EINVAL, "plan was made on device %d, current device is %d", plan->device, dev);
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  switch (plan->dp.dtype) {
+    case HP_F32: return hp::launch_nest_f32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st);
+    case HP_BF16: return hp::launch_nest_bf16(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st);
+    default: return hp::launch_nest_i32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st);
+  }
+}
+
+extern "C" hp_status hp_destroy(hp_plan_t plan) {
+  if (!plan) return HP_OK;
+  hp_status s = HP_OK;
+  if (plan->ws && hipFree(plan->ws) != hipSuccess) s = hp::fail(HP_EDEVICE, "workspace free failed");
+  if (plan->d_dp && hipFree(plan->d_dp) != hipSuccess) s = hp::fail(HP_EDEVICE, "device plan free failed");
+  delete plan;
+  return s;
+}

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on seeded
+inputs.  Integer, MIN/MAX and ARG results must be bit-exact; float sums must be
+within |got - ref| <= 1e-6 * max(|ref|, 2^-24 * sum|a|) of the fp64 oracle."""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import assert_match, gpu_reduce, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    import paper_2309_01906_amd as hp
+    hp.lib()  # fails loudly if libhp.so is missing
+    yield
+
+
+# --------------------------------------------------------------------------
+# the workloads at their full sizes
+
+
+def test_c1_full_bit_exact():
+    say("case c1 1024x1024 int32 SUM")
+    x = workloads.c1_input()
+    got, info = gpu_reduce(x, x.shape, ("NONE", "SUM"))
+    assert_match(got, x, x.shape, ("NONE", "SUM"), what="c1")
+
+
+def test_c2_reduced_rows_full_parity():
+    say("case c2 shape 64x256x256 fp32")
+    x = workloads.c2_input((64, 256, 256))
+    got, info = gpu_reduce(x, x.shape, ("NONE", "SUM", "SUM"))
+    assert got.dtype == np.float64
+    assert_match(got, x, x.shape, ("NONE", "SUM", "SUM"), what="c2 small")
+
+
+def test_c2_full_size_sampled_rows():
+    say("case c2 full 4096x256x256 fp32 (1 GiB)")
+    x = workloads.c2_input()
+    got, info = gpu_reduce(x, x.shape, ("NONE", "SUM", "SUM"))
+    assert np.all(np.isfinite(got))
+    rows = sorted(set([0, 1, 2, 4095, 2047, 2048] + list(range(7, 4096, 131))))
+    for r in rows:
+        assert_match(got[r:r + 1], x, x.shape, ("NONE", "SUM", "SUM"), o_begin=r, o_end=r + 1, what=f"c2 row {r}")
+
+
+C3_OPS = ("NONE", "SUM", "MAX", "ARGMIN")
+C3_MAPS = [
+    None,
+    ["G", "W", "V", "L"],                                   # the literal map of the workload
+    ["G", ("GW", {"G": 8, "W": 4}), "V", "L"],              # level 1 split over the grid
+    ["G", "W", ("V", {"V": 4}), ("V", {"V": 16})],          # partitions of 16 lanes
+    ["G", ("W", {"W": 16}), "L", "L"],                       # lanes idle: level 2 and 3 serial
+    ["G", "GW", ("WV", {"W": 2, "V": 8}), ("V", {"V": 8})],  # waves split between two levels
+    [("GW", {"G": 16, "W": 4}), "L", "L", "L"],              # outputs over workgroups and waves
+]
+
+
+def test_c3_full_bit_exact_and_map_independent():
+    x = workloads.c3_input()
+    first = None
+    for m in C3_MAPS:
+        say("case c3 map", m)
+        got, info = gpu_reduce(x, x.shape, C3_OPS, m)
+        if first is None:
+            assert_match(got, x, x.shape, C3_OPS, what=f"c3 map {m}")
+            first = got
+        else:
+            np.testing.assert_array_equal(got, first, err_msg=f"c3 map {m}")
+
+
+# --------------------------------------------------------------------------
+# every monotone map of small nests, integer and float, ragged extents
+
+SCOPE_SETS = ["G", "W", "V", "L", "GW", "WV", "VL", "GWV", "WVL", "GWVL"]
+ORDER = "GWVL"
+
+
+def monotone(m):
+    for i, b in enumerate(m):
+        for a in m[:i]:
+            hi = a[-1] if a == "L" else a.replace("L", "")[-1]
+            if ORDER.index(b[0]) < ORDER.index(hi):
+                return False
+    return True
+
+
+def maps(depth):
+    return [list(m) for m in itertools.product(SCOPE_SETS, repeat=depth) if monotone(m)]
+
+
+INT_CHAINS_2 = [("NONE", "SUM"), ("NONE", "MIN"), ("NONE", "ARGMAX"), ("SUM", "SUM"), ("ARGMIN", "SUM"),
+                ("NONE", "NONE")]
+INT_CHAINS_3 = [("NONE", "SUM", "SUM"), ("NONE", "MAX", "ARGMIN"), ("NONE", "SUM", "MIN"), ("SUM", "ARGMAX", "MAX"),
+                ("NONE", "NONE", "ARGMIN")]
+
+
+@pytest.mark.parametrize("depth", [2, 3])
+def test_all_maps_int(depth):
+    import paper_2309_01906_amd as hp
+    ext = (5, 37) if depth == 2 else (3, 7, 36)
+    chains = INT_CHAINS_2 if depth == 2 else INT_CHAINS_3
+    x = workloads.uniform_i32(40 + depth, ext, -3, 3)
+    dev = to_device(x)
+    n = 0
+    for ops in chains:
+        for m in maps(depth):
+            try:
+                got, info = gpu_reduce(x, ext, ops, m, dev=dev)
+            except hp.HPError as e:
+                assert e.status_name == "HP_EUNSUPPORTED", (ops, m, str(e))
+                continue
+            assert_match(got, x, ext, ops, what=f"ops {ops} map {m}")
+            n += 1
+    say("int maps checked:", n)
+    assert n > 50
+
+
+@pytest.mark.parametrize("depth", [2, 3])
+def test_all_maps_float(depth):
+    import paper_2309_01906_amd as hp
+    ext = (5, 1000) if depth == 2 else (3, 9, 68)
+    x = workloads.normal_f32(50 + depth, ext)
+    dev = to_device(x)
+    n = 0
+    for ops in [("NONE",) + ("SUM",) * (depth - 1), ("SUM",) * depth]:
+        for m in maps(depth):
+            try:
+                got, info = gpu_reduce(x, ext, ops, m, dev=dev)
+            except hp.HPError as e:
+                assert e.status_name == "HP_EUNSUPPORTED", (ops, m, str(e))
+                continue
+            assert_match(got, x, ext, ops, what=f"ops {ops} map {m}")
+            n += 1
+    say("float maps checked:", n)
+
+
+def test_depth4_maps_sampled():
+    ext = (3, 5, 6, 12)
+    x = workloads.uniform_i32(61, ext, 0, 5)
+    dev = to_device(x)
+    rng = np.random.default_rng(3)
+    all4 = maps(4)
+    picks = [all4[i] for i in rng.choice(len(all4), size=min(120, len(all4)), replace=False)]
+    for ops in [C3_OPS, ("NONE", "ARGMAX", "MIN", "SUM"), ("NONE", "NONE", "SUM", "SUM")]:
+        for m in picks:
+            try:
+                got, _ = gpu_reduce(x, ext, ops, m, dev=dev)
+            except Exception as e:  # only unsupported maps may be refused
+                assert "HP_EUNSUPPORTED" in str(e), (ops, m, str(e))
+                continue
+            assert_match(got, x, ext, ops, what=f"ops {ops} map {m}")
+
+
+# --------------------------------------------------------------------------
+# edge cases
+
+
+@pytest.mark.parametrize("ext,ops", [
+    ((1,), ("SUM",)), ((1,), ("NONE",)), ((37,), ("NONE",)), ((1, 1, 1), ("NONE", "SUM", "ARGMIN")),
+    ((5, 1), ("NONE", "ARGMAX")), ((1, 100003), ("NONE", "SUM")), ((3, 1, 64), ("NONE", "MAX", "SUM")),
+    ((2, 3, 1, 5, 7), ("NONE", "SUM", "MAX", "ARGMIN", "SUM")),
+    ((2, 2, 2, 2, 2, 2, 2, 5), ("NONE",) + ("SUM", "MAX", "ARGMIN", "SUM", "MIN", "ARGMAX", "MAX")),
+    ((1, 1 << 22), ("NONE", "SUM")), ((1, 1 << 22), ("NONE", "ARGMIN")),
+])
+def test_edge_shapes_int(ext, ops):
+    say("case edge int", ext, ops)
+    x = workloads.uniform_i32(70, ext, -(2**31), 2**31 - 1)
+    got, _ = gpu_reduce(x, ext, ops)
+    assert_match(got, x, ext, ops, what=f"{ext} {ops}")
+
+
+@pytest.mark.parametrize("ext,ops", [
+    ((1,), ("SUM",)), ((7, 3), ("NONE", "NONE")), ((1, 1 << 22), ("NONE", "SUM")), ((3, 1001), ("NONE", "SUM")),
+    ((2, 3, 5, 7, 11), ("NONE", "SUM", "SUM", "SUM", "SUM")), ((1, 1 << 26), ("NONE", "SUM")),
+])
+def test_edge_shapes_float(ext, ops):
+    say("case edge float", ext, ops)
+    x = workloads.normal_f32(71, ext)
+    got, _ = gpu_reduce(x, ext, ops)
+    assert_match(got, x, ext, ops, what=f"{ext} {ops}")
+
+
+def test_int_sum_of_int32_min_needs_64_bits():
+    x = np.full((4, 4096), np.iinfo(np.int32).min, np.int32)
+    got, _ = gpu_reduce(x, x.shape, ("NONE", "SUM"))
+    np.testing.assert_array_equal(got, np.full(4, -(2**31) * 4096, np.int64))
+
+
+def test_argmin_ties_first_occurrence():
+    for ext in [(8, 64), (4, 1 << 20), (2, 3, 1000)]:
+        x = workloads.uniform_i32(72, ext, 0, 1)
+        ops = ("NONE",) * (len(ext) - 1) + ("ARGMIN",)
+        got, _ = gpu_reduce(x, ext, ops)
+        assert_match(got, x, ext, ops, what=f"ties {ext}")
+
+
+def test_flags_scalar_out_f32_temporal_noxcd():
+    import paper_2309_01906_amd as hp
+    x = workloads.normal_f32(73, (256, 4096))
+    for fl in [hp.FLAG_SCALAR, hp.FLAG_OUT_F32, hp.FLAG_TEMPORAL, hp.FLAG_NO_XCD]:
+        got, info = gpu_reduce(x, x.shape, ("NONE", "SUM"), flags=fl)
+        if fl == hp.FLAG_OUT_F32:
+            assert got.dtype == np.float32
+        assert_match(got.astype(np.float64), x, x.shape, ("NONE", "SUM"), what=f"flag {fl}")
+    xi = workloads.uniform_i32(74, (256, 4096), -5, 5)
+    got, _ = gpu_reduce(xi, xi.shape, ("NONE", "ARGMAX"), flags=hp.FLAG_SCALAR)
+    assert_match(got, xi, xi.shape, ("NONE", "ARGMAX"), what="int scalar")
+
+
+def test_bf16_nests():
+    for ext in [(4, 64, 64), (64, 3, 64), (1, 2048, 64), (3, 5, 8), (2, 7)]:
+        x = workloads.normal_bf16_bits(75, ext)
+        ops = ("NONE",) + ("SUM",) * (len(ext) - 1)
+        got, _ = gpu_reduce(x, ext, ops)
+        assert_match(got, x, ext, ops, what=f"bf16 {ext}")
+
+
+def test_grid_combine_nested_segments():
+    # level 1 (ARGMAX) and level 2 (SUM) both span workgroups: partials folded per
+    # output in nest order by the last workgroup
+    ext = (3, 5, 4096)
+    x = workloads.uniform_i32(76, ext, -100, 100)
+    for ops, m in [(("NONE", "ARGMAX", "SUM"), ["G", "G", ("GWV", {"G": 4})]),
+                   (("NONE", "MIN", "SUM"), ["G", ("G", {"G": 5}), ("GW", {"G": 8, "W": 2})]),
+                   (("NONE", "SUM", "MAX"), ["G", ("G", {"G": 8}), ("GV", {"G": 3})])]:
+        got, info = gpu_reduce(x, ext, ops, m)
+        assert info["gsplit"] > 1
+        assert_match(got, x, ext, ops, what=f"nested {ops} {m}")
+
+
+def test_plan_reuse_and_determinism():
+    import paper_2309_01906_amd as hp
+    x1 = workloads.normal_f32(77, (4, 1 << 20))
+    x2 = workloads.normal_f32(78, (4, 1 << 20))
+    d1, d2 = to_device(x1), to_device(x2)
+    with hp.Plan((4, 1 << 20), (0, 1), hp.F32) as p:
+        assert p.info["gsplit"] > 1
+        outs = []
+        for d in (d1, d2, d1, d1):
+            outs.append(p.run(d).cpu().numpy())
+    assert_match(outs[0], x1, x1.shape, ("NONE", "SUM"), what="reuse 1")
+    assert_match(outs[1], x2, x2.shape, ("NONE", "SUM"), what="reuse 2")
+    np.testing.assert_array_equal(outs[0], outs[2])
+    np.testing.assert_array_equal(outs[0], outs[3])
+
+
+def test_run_rejects_bad_pointers():
+    import ctypes
+
+    import paper_2309_01906_amd as hp
+    x = to_device(workloads.uniform_i32(79, (16, 64), 0, 9))
+    with hp.Plan((16, 64), (0, 1), hp.I32) as p:
+        out = p.empty_out(x.device)
+        st = hp.lib().hp_run(p._h, ctypes.c_void_p(x.data_ptr() + 4), ctypes.c_void_p(out.data_ptr()), None)
+        assert hp.STATUS[st] == "HP_EINVAL"
+        st = hp.lib().hp_run(p._h, None, ctypes.c_void_p(out.data_ptr()), None)
+        assert hp.STATUS[st] == "HP_EINVAL"
+        st = hp.lib().hp_run(None, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), None)
+        assert hp.STATUS[st] == "HP_EINVAL"

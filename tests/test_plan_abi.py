@@ -1,0 +1,132 @@
+"""Host-side tests of libhp.so: every declared entry point is exported, and the
+planner (host only, no device) validates nests and maps and lowers them to
+consistent launch geometry."""
+import itertools
+import os
+import re
+
+import pytest
+
+import paper_2309_01906_amd as hp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(hp_\w+)\s*\(", txt, re.M))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = hp.lib()
+    names = declared_functions()
+    assert "hp_plan" in names and "hp_run" in names and "hp_destroy" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = hp.lib()
+    for i, name in enumerate(hp.STATUS):
+        assert L.hp_status_str(i).decode() == name
+
+
+def err(extents, ops, dtype, m=None, flags=0):
+    with pytest.raises(hp.HPError) as e:
+        hp.inspect(extents, ops, dtype, m, flags)
+    return e.value.status_name
+
+
+def test_rejects_malformed_nests():
+    assert err((4, 0), ("NONE", "SUM"), hp.I32) == "HP_EINVAL"
+    assert err((4, 4), ("SUM", "NONE"), hp.I32) == "HP_EINVAL"
+    assert err((4, 4), ("NONE", "MAX"), hp.F32) == "HP_EUNSUPPORTED"
+    assert err((4, 4), ("NONE", "ARGMIN"), hp.BF16) == "HP_EUNSUPPORTED"
+    assert err((4, 4), ("NONE", 9), hp.I32) == "HP_EINVAL"
+    assert err((4, 4), ("NONE", "SUM"), 7) == "HP_EINVAL"
+    assert err((4, 4), ("NONE", "SUM"), hp.I32, flags=0x100) == "HP_EINVAL"
+
+
+def test_rejects_bad_maps():
+    n = ((8, 8, 8), ("NONE", "SUM", "SUM"), hp.I32)
+    assert err(*n, m=["W", "G", "V"]) == "HP_EINVAL"            # not monotone
+    assert err(*n, m=["G", "GV", "L"]) == "HP_EINVAL"           # G+V is not a run of adjacent scopes
+    assert err(*n, m=["G", ("W", {"W": 3}), "V"]) == "HP_EINVAL"  # not a power of two
+    assert err(*n, m=["G", ("W", {"W": 32}), "V"]) == "HP_EINVAL"  # more than 16 waves
+    assert err(*n, m=["G", ("W", {"V": 4}), "V"]) == "HP_EINVAL"  # units on an unused axis
+    assert err(*n, m=["G", ("V", {"V": 16}), ("V", {"V": 16})]) == "HP_EINVAL"  # 256 lanes
+    assert err(*n, m=["", "W", "V"]) == "HP_EINVAL"
+
+
+SCOPE_SETS = ["G", "W", "V", "L", "GW", "WV", "VL", "GWV", "WVL", "GWVL"]
+ORDER = "GWVL"
+
+
+def monotone(m):
+    # an L next to other scopes only marks strips; a level on L alone is serial
+    for i, b in enumerate(m):
+        for a in m[:i]:
+            hi = a[-1] if a == "L" else a.replace("L", "")[-1]
+            if ORDER.index(b[0]) < ORDER.index(hi):
+                return False
+    return True
+
+
+def all_maps(depth):
+    return [m for m in itertools.product(SCOPE_SETS, repeat=depth) if monotone(m)]
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_every_monotone_map_plans_consistently(depth):
+    ext = (5, 7, 33)[:depth]
+    for ops in [("SUM",) * depth, ("NONE",) + ("MAX",) * (depth - 1), ("NONE",) * depth]:
+        for m in all_maps(depth):
+            try:
+                info = hp.inspect(ext, ops, hp.I32, list(m))
+            except hp.HPError as e:
+                # only the one-strip rule for reducing levels outside a grid-spanning
+                # segment may refuse a well-formed monotone map
+                assert e.status_name == "HP_EUNSUPPORTED", (m, ops, str(e))
+                continue
+            for l in range(depth):
+                g, w, v = info["units"][l]
+                chunk = info["chunk"] if l == depth - 1 else 1
+                span = g * w * v * chunk
+                assert info["strips"][l] == -(-ext[l] // span)
+                assert (g > 1) <= ("G" in m[l]) and (w > 1) <= ("W" in m[l]) and (v > 1) <= ("V" in m[l])
+            assert 1 <= info["waves"] <= 16
+            assert info["grid"] >= 1
+
+
+def test_auto_maps_for_the_workloads():
+    c1 = hp.inspect((1024, 1024), ("NONE", "SUM"), hp.I32)
+    assert c1["n_out"] == 1024 and c1["out_dtype"] == hp.I64 and c1["chunk"] == 4
+    c2 = hp.inspect((4096, 256, 256), ("NONE", "SUM", "SUM"), hp.F32)
+    assert c2["grid"] == 4096 and c2["gsplit"] == 1 and c2["out_dtype"] == hp.F64
+    assert c2["map"][2] == "V" and c2["map"][1] == "W"
+    c3 = hp.inspect((64, 128, 64, 64), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32)
+    assert c3["nseg"] == 3 and c3["out_dtype"] == hp.I64 and c3["gsplit"] > 1
+    big = hp.inspect((1, 1 << 28), ("NONE", "SUM"), hp.F32)
+    assert big["gsplit"] > 1 and big["workspace_bytes"] > 0
+
+
+def test_output_types_match_the_oracle_rule():
+    import oracle
+    for ops in [("NONE", "SUM"), ("NONE", "MAX"), ("NONE", "ARGMAX"), ("NONE", "MIN", "SUM"),
+                ("NONE", "MAX", "ARGMIN", "SUM"), ("NONE", "SUM", "MAX", "ARGMIN"), ("NONE",), ("SUM", "MIN")]:
+        ext = (3,) * len(ops)
+        kind = oracle.out_kind(ext, [hp.OP_NAMES[o] for o in ops], 0)
+        got = hp.inspect(ext, ops, hp.I32)["out_dtype"]
+        assert got == {0: hp.I32, 1: hp.I64}[kind], ops
+    assert hp.inspect((3, 3), ("NONE", "SUM"), hp.F32, flags=hp.FLAG_OUT_F32)["out_dtype"] == hp.F32
+
+
+def test_scalar_chunk_when_extent_is_ragged():
+    assert hp.inspect((4, 6), ("NONE", "SUM"), hp.F32)["chunk"] == 1
+    assert hp.inspect((4, 7), ("NONE", "SUM"), hp.F32)["chunk"] == 1
+    assert hp.inspect((4, 8), ("NONE", "SUM"), hp.BF16)["chunk"] == 8
+    assert hp.inspect((4, 8), ("NONE", "SUM"), hp.F32, flags=hp.FLAG_SCALAR)["chunk"] == 1
