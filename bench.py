@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the nested multi-level reduction on one MI355X.
+
+Headline workload: the plain 3-level nest, fp32 4096 x 256 x 256 (1 GiB, N(0,1)),
+out[i] = sum_j sum_k A[i,j,k] with fp32 compensated accumulation and fp64 output,
+levels mapped grid -> waves -> lanes.  A step is one hp_run over the whole array
+(input resident in HBM); value = algorithmic bytes (input + output) per second.
+
+Prints ONE JSON line (rank 0, N = 1).  Only one GPU is used; --gpus > 1 exits.
+The CPU baseline leg times the oracle (test infrastructure) on the host cores and
+states the error of the GPU result against it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "achieved HBM GB/s (% of peak) for nested reduction; batched-vs-plain; p50/p99"
+PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+KERNEL_SOURCES = ["hp_nest.h", "hp_nest_f32.hip", "hp_internal.h", "hp_plan.cpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2309_01906_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[k]
+
+
+def time_plan(plan, dev_in, out, steps, warmup, stream):
+    """Warmup, then `steps` runs bracketed by synchronize; per-run HIP events on the
+    stream the kernel is launched on."""
+    import torch
+    for _ in range(warmup):
+        plan.run(dev_in, out, stream=stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        plan.run(dev_in, out, stream=stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall, ev_ms
+
+
+def traffic_from_profiles(per_launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "c2_nest_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(x_host, ext, ops, got_rows):
+    """Oracle on the host cores: the full workload with every core (median of 3),
+    plus the error statement of the GPU result against it."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(64, os.cpu_count() or 1))
+    n_out = ext[0]
+    times = []
+    ref = None
+    budget = 25.0
+    t_start = time.perf_counter()
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ref = oracle.reduce(x_host, ext, ops, oracle.F32, threads=threads)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget:
+            break
+    t = statistics.median(times)
+    nbytes = x_host.nbytes + n_out * 8
+    s = oracle.abs_sum(x_host, ext, ops, oracle.F32, threads=threads)
+    ok, plain, scaled = oracle.within_tolerance(got_rows, ref, s, 1e-6)
+    return {
+        "value": round(nbytes / t / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+        "sample": f"full workload ({n_out} outputs, {x_host.nbytes >> 20} MiB), median of {len(times)} runs, "
+                  f"fp64 Neumaier sequential C, outputs split over {threads} threads",
+        "seconds": round(t, 4),
+    }, {"all_outputs_checked": int(n_out), "within_1e-6": ok, "max_rel_err": plain,
+        "max_scaled_err": scaled}
+
+
+def extra_int_workloads(steps, warmup, stream):
+    """C1 and C3: GB/s with the plan's default map (cache-resident sizes: labelled)."""
+    import torch
+
+    import paper_2309_01906_amd as hp
+    import workloads
+    res = {}
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    for name, nest, gen in (("c1", workloads.C1, workloads.c1_input), ("c3", workloads.C3, workloads.c3_input)):
+        x = gen()
+        d = torch.from_numpy(x).cuda()
+        with hp.Plan(nest.extents, nest.ops, nest.dtype) as p:
+            out = p.empty_out(d.device)
+            # warm (cache-resident) timing
+            wall, ev = time_plan(p, d, out, steps, warmup, stream)
+            # cold: flush L2 / MALL with a 512 MiB fill between runs, outside the events
+            cold = []
+            for _ in range(min(steps, 50)):
+                flush.fill_(1)
+                s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s.record(stream)
+                p.run(d, out, stream=stream)
+                e.record(stream)
+                torch.cuda.synchronize()
+                cold.append(s.elapsed_time(e))
+            nbytes = x.nbytes + p.info["out_bytes"]
+            res[name] = {
+                "shape": list(nest.extents), "bytes": nbytes, "map": p.info["map"], "grid": p.info["grid"],
+                "warm_p50_us": round(pct(ev, 50) * 1e3, 2), "warm_p99_us": round(pct(ev, 99) * 1e3, 2),
+                "cold_p50_us": round(pct(cold, 50) * 1e3, 2), "cold_p99_us": round(pct(cold, 99) * 1e3, 2),
+                "cold_GBps": round(nbytes / (pct(cold, 50) * 1e-3) / 1e9, 1),
+            }
+        del d
+    del flush
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2309_01906_amd as hp
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    nest = workloads.C2
+    x_host = workloads.c2_input()
+    dev_in = torch.from_numpy(x_host).cuda()
+    plan = hp.Plan(nest.extents, nest.ops, nest.dtype)
+    out = plan.empty_out(dev_in.device)
+    wall, ev_ms = time_plan(plan, dev_in, out, args.steps, args.warmup, stream)
+    nbytes = x_host.nbytes + plan.info["out_bytes"]
+    ms_per_step = wall / args.steps * 1e3
+    value = nbytes / (ms_per_step * 1e-3) / 1e9
+    avg_ev = sum(ev_ms) / len(ev_ms)
+    achieved = nbytes / (avg_ev * 1e-3) / 1e9
+    got = out.cpu().numpy()
+
+    if args.copy_calib:
+        y = torch.empty_like(dev_in)
+        y.copy_(dev_in)
+        torch.cuda.synchronize()
+        del y
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain 3-level nest fp32 4096x256x256 (1 GiB, N(0,1)), out[i]=sum_j sum_k A, "
+                               "fp32 compensated pairs, fp64 output; grid->waves->lanes",
+                   "shape": list(nest.extents), "map": plan.info["map"], "units": plan.info["units"],
+                   "waves_per_workgroup": plan.info["waves"], "grid": plan.info["grid"],
+                   "algorithmic_bytes": nbytes, "parallelism": "1 GPU"},
+        "pct_of_peak": round(100.0 * value / PEAK_GBS, 2),
+        "p50_us": round(pct(ev_ms, 50) * 1e3, 2), "p99_us": round(pct(ev_ms, 99) * 1e3, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic_from_profiles(nbytes),
+                     "kernel": "hp::k_nest_f32<4,4>", "algorithmic_bytes_per_launch": nbytes,
+                     "kernel_hash": kernel_hash()},
+    }
+    if not args.no_cpu_baseline:
+        cb, err = cpu_baseline(x_host, nest.extents, nest.ops, got)
+        line["cpu_baseline"] = cb
+        line["error_vs_fp64_oracle"] = err
+    if not args.no_extras:
+        line["extras"] = extra_int_workloads(min(args.steps, 200), min(args.warmup, 20), stream)
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,148 @@ hp_status hp_run(hp_plan_t plan, const void* d_in, void* d_out, void* stream);
  * sure no launch using the plan is still running. */
 hp_status hp_destroy(hp_plan_t plan);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many nests of uneven sizes in one persistent launch per kernel family.
+ * Workgroups take (nest, workgroup) tasks from one atomic counter -- a dynamic
+ * schedule on the grid level (section 3.5), the one synchronisation it needs --
+ * largest tasks first.  Every nest keeps the plan it would get alone (its own
+ * shape and the tuner cache decide it, never the batch), so its result is the
+ * same bits as a single run of that plan.
+ */
+typedef struct hp_batch_s* hp_batch_t;
+
+#define HP_BATCH_GRAPH 0x100u   /* hp_batch_run replays a captured hipGraph */
+#define HP_BATCH_NO_TUNE 0x200u /* ignore the tuner cache: automatic maps only */
+
+/* Plan n nests (each validated as by hp_plan_inspect; batched plans use 4 waves
+ * per workgroup) and allocate the batch's device tables, task lists, counters and
+ * grid-combine workspaces.  flags: HP_BATCH_GRAPH, HP_BATCH_NO_TUNE,
+ * HP_FLAG_OUT_F32, HP_FLAG_TEMPORAL.  HP_EINVAL / HP_EUNSUPPORTED name the first
+ * bad nest; HP_ENOMEM if device memory runs out. */
+hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t flags, hp_batch_t* out);
+
+/* Planner decisions for nest i of the batch. */
+hp_status hp_batch_info(hp_batch_t b, int64_t i, hp_plan_info* info);
+
+/* Launch count (persistent kernels per run), total workgroup tasks, and the
+ * algorithmic bytes (inputs + outputs) of one run. */
+hp_status hp_batch_stats(hp_batch_t b, int64_t* n_launches, int64_t* n_tasks, double* bytes);
+
+/* Point the batch at its data: host arrays of n device pointers (inputs 16-byte
+ * aligned, outputs aligned for their type).  Copied into the batch's device
+ * table (synchronous); a captured graph stays valid across calls. */
+hp_status hp_batch_set_io(hp_batch_t b, const void* const* d_in, void* const* d_out);
+
+/* Run all nests: one persistent launch per kernel family (or one graph launch
+ * with HP_BATCH_GRAPH, captured at the first call).  Asynchronous on `stream`;
+ * must not overlap another run of the same batch.  HP_ESTATE before set_io. */
+hp_status hp_batch_run(hp_batch_t b, void* stream);
+
+/* Baseline: the same plans, one launch per nest (use_graph: all of those launches
+ * captured once in one graph and replayed). */
+hp_status hp_batch_run_each(hp_batch_t b, void* stream, int32_t use_graph);
+
+/* Free the batch (the caller makes sure no run is in flight).  NULL is a no-op. */
+hp_status hp_batch_destroy(hp_batch_t b);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner (section 3.9's choice between kernel versions, made by measurement):
+ * for a nest whose reducing levels fold as one reduction (SUM, MIN or MAX), time
+ * candidate level maps of its size class on the current device -- the block seen
+ * as (J, K) rows, J split between grid, waves and lane partitions -- and store the
+ * fastest in the process-wide cache that batched plans consult.  Timings are
+ * medians of `reps` runs.  best_us / auto_us (may be NULL) receive the winner's
+ * time and the automatic map's.  The cache is also read once from the file named
+ * by the HP_TUNE_CACHE environment variable. */
+hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t reps, double* best_us, double* auto_us);
+hp_status hp_tune_cache_load(const char* path);
+hp_status hp_tune_cache_save(const char* path);
+hp_status hp_tune_cache_clear(void);
+hp_status hp_tune_cache_size(int64_t* n);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of nest-reduction requests (not in the paper: the
+ * serving form of the batched kernel).  Requests arrive at any time; a scheduler
+ * thread admits them in arrival order while their bytes (input + output + grid
+ * workspace) fit the HBM budget -- a request that does not fit may be passed by
+ * later ones at most 64 times -- and launches a batch as soon as one of `streams`
+ * slots is free and either max_batch requests wait, the oldest has waited
+ * window_us, or the device is idle.  Batches of different slots overlap on the
+ * device.  Request state (plans, task lists, partials, tickets) lives in the
+ * slot's device arena.  Each request keeps the plan it would get alone, so its
+ * result does not depend on the batch it ran in.  Payloads are not copied: d_in
+ * and d_out must stay valid until the request completes.
+ */
+typedef struct hp_server_s* hp_server_t;
+
+#define HP_SERVER_FAKE_DEVICE 0x1000u /* host-only executor for scheduler tests: no GPU work */
+
+typedef struct hp_server_cfg {
+  size_t hbm_budget;              /* bytes admitted at once */
+  size_t slot_bytes;              /* device arena per slot (descriptors + workspaces of one batch) */
+  int32_t streams;                /* slots = batches in flight, 1..16 */
+  int32_t max_batch;              /* requests per batch */
+  int32_t window_us;              /* how long a partial batch may wait while the device is busy */
+  int32_t queue_cap;              /* pending requests before hp_submit returns HP_EAGAIN */
+  uint32_t flags;                 /* HP_FLAG_OUT_F32, HP_FLAG_TEMPORAL, HP_SERVER_FAKE_DEVICE */
+  int32_t fail_every_nth_batch;   /* test hook: every n-th batch fails without running (0: never) */
+} hp_server_cfg;
+
+typedef struct hp_req_info {
+  int32_t status;      /* HP_ENOTREADY while pending / in flight, then HP_OK or the failure */
+  int32_t pad;
+  double t_arrival_us; /* server clock (hp_server_now_us) */
+  double t_admit_us;
+  double t_launch_us;
+  double t_done_us;    /* when the scheduler saw the batch complete */
+  int64_t bytes;       /* algorithmic bytes: input + output */
+  int64_t batch_id;
+} hp_req_info;
+
+typedef struct hp_server_stats {
+  int64_t submitted, completed, failed, batches, pending, max_queue;
+  int64_t max_in_use_bytes, in_use_bytes;
+  double bytes;                          /* input + output bytes of completed requests */
+  double p50_us, p99_us, p999_us, max_us, mean_us; /* arrival -> completion latency */
+  double gbps;                           /* bytes / (last completion - first arrival) */
+} hp_server_stats;
+
+/* Start a server on the current device (allocates its slots' streams, events,
+ * device arenas and pinned staging).  HP_EINVAL for a bad configuration. */
+hp_status hp_server_create(const hp_server_cfg* cfg, hp_server_t* out);
+
+/* Submit one request; t_arrival_us < 0 stamps the current server time (an
+ * open-loop client passes its scheduled arrival time instead).  The nest is
+ * planned here (errors as hp_plan_inspect).  HP_ETOOBIG if it alone exceeds the
+ * budget, HP_EAGAIN if the queue is full, HP_ESTATE after shutdown began. */
+hp_status hp_submit(hp_server_t s, const hp_nest* nest, const void* d_in, void* d_out, double t_arrival_us,
+                    uint64_t* ticket);
+
+/* HP_ENOTREADY until the request completed; then HP_OK with info filled (its
+ * status field holds the request's own outcome). */
+hp_status hp_poll(hp_server_t s, uint64_t ticket, hp_req_info* info);
+
+/* Block until the request completed. */
+hp_status hp_wait(hp_server_t s, uint64_t ticket, hp_req_info* info);
+
+/* Drop a completed request's record. */
+hp_status hp_server_forget(hp_server_t s, uint64_t ticket);
+
+/* Counters and latency percentiles of the completed requests. */
+hp_status hp_server_get_stats(hp_server_t s, hp_server_stats* st);
+
+/* Current server clock in microseconds. */
+hp_status hp_server_now_us(hp_server_t s, double* t);
+
+/* Open-loop client: submit request i at server time t_arrival_us[i] (ascending),
+ * without waiting for completions; tickets[i] receives its ticket. */
+hp_status hp_server_replay(hp_server_t s, int64_t n, const hp_nest* nests, const void* const* d_in,
+                           void* const* d_out, const double* t_arrival_us, uint64_t* tickets);
+
+/* Drain: finish every admitted and pending request, stop the scheduler, free the
+ * slots.  NULL is a no-op. */
+hp_status hp_server_destroy(hp_server_t s);
+
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* hp_last_error(void);
 

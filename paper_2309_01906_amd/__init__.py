@@ -239,3 +239,247 @@ def reduce(inp, extents, ops, level_map=None, flags: int = 0, stream=None):
     _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     p.close()
     return out
+
+
+# ---------------------------------------------------------------------------
+# batches and the autotuner
+
+BATCH_GRAPH, BATCH_NO_TUNE = 0x100, 0x200
+_batch_sigs_done = False
+
+
+def _batch_sigs():
+    global _batch_sigs_done
+    if _batch_sigs_done:
+        return
+    L = lib()
+    vp, st = ctypes.c_void_p, ctypes.c_int
+    L.hp_batch_plan.argtypes = [ctypes.POINTER(Nest), ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.hp_batch_info.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(PlanInfo)]
+    L.hp_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_double)]
+    L.hp_batch_set_io.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.hp_batch_run.argtypes = [vp, vp]
+    L.hp_batch_run_each.argtypes = [vp, vp, ctypes.c_int32]
+    L.hp_batch_destroy.argtypes = [vp]
+    L.hp_tune_nest.argtypes = [ctypes.POINTER(Nest), ctypes.c_uint32, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.hp_tune_cache_load.argtypes = [ctypes.c_char_p]
+    L.hp_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.hp_tune_cache_clear.argtypes = []
+    L.hp_tune_cache_size.argtypes = [ctypes.POINTER(ctypes.c_int64)]
+    for f in ("hp_batch_plan", "hp_batch_info", "hp_batch_stats", "hp_batch_set_io", "hp_batch_run",
+              "hp_batch_run_each", "hp_batch_destroy", "hp_tune_nest", "hp_tune_cache_load",
+              "hp_tune_cache_save", "hp_tune_cache_clear", "hp_tune_cache_size"):
+        getattr(L, f).restype = st
+    _batch_sigs_done = True
+
+
+class Batch:
+    """hp_batch_*: many nests, one persistent launch per kernel family."""
+
+    def __init__(self, nests, flags: int = 0):
+        _batch_sigs()
+        arr = (Nest * len(nests))()
+        for i, (ext, ops, dt) in enumerate(nests):
+            arr[i] = make_nest(ext, ops, dt)
+        self._h = ctypes.c_void_p()
+        self.n = len(nests)
+        check(lib().hp_batch_plan(arr, self.n, flags, ctypes.byref(self._h)))
+
+    def info(self, i: int) -> dict:
+        inf = PlanInfo()
+        check(lib().hp_batch_info(self._h, i, ctypes.byref(inf)))
+        return _info_dict(inf)
+
+    def stats(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(lib().hp_batch_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"launches": a.value, "tasks": b.value, "bytes": c.value}
+
+    def set_io_ptrs(self, in_ptrs, out_ptrs):
+        ins = (ctypes.c_void_p * self.n)(*in_ptrs)
+        outs = (ctypes.c_void_p * self.n)(*out_ptrs)
+        check(lib().hp_batch_set_io(self._h, ins, outs))
+
+    def set_io(self, ins, outs):
+        self.set_io_ptrs([t.data_ptr() for t in ins], [t.data_ptr() for t in outs])
+
+    def run(self, stream=None):
+        check(lib().hp_batch_run(self._h, _stream_handle(stream)))
+
+    def run_each(self, stream=None, graph: bool = False):
+        check(lib().hp_batch_run_each(self._h, _stream_handle(stream), 1 if graph else 0))
+
+    def close(self):
+        if self._h:
+            check(lib().hp_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.hp_batch_destroy(self._h)
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def tune(extents, ops, dtype, reps: int = 20, flags: int = 0):
+    """Time candidate maps for the nest's size class on the current device and
+    cache the fastest; returns (best_us, auto_us)."""
+    _batch_sigs()
+    n = make_nest(extents, ops, dtype)
+    b, a = ctypes.c_double(), ctypes.c_double()
+    check(lib().hp_tune_nest(ctypes.byref(n), flags, reps, ctypes.byref(b), ctypes.byref(a)))
+    return b.value, a.value
+
+
+def tune_cache_load(path: str):
+    _batch_sigs()
+    check(lib().hp_tune_cache_load(path.encode()))
+
+
+def tune_cache_save(path: str):
+    _batch_sigs()
+    check(lib().hp_tune_cache_save(path.encode()))
+
+
+def tune_cache_clear():
+    _batch_sigs()
+    check(lib().hp_tune_cache_clear())
+
+
+def tune_cache_size() -> int:
+    _batch_sigs()
+    n = ctypes.c_int64()
+    check(lib().hp_tune_cache_size(ctypes.byref(n)))
+    return n.value
+
+
+# ---------------------------------------------------------------------------
+# serving
+
+SERVER_FAKE_DEVICE = 0x1000
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("slot_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("window_us", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("fail_every_nth_batch", ctypes.c_int32)]
+
+
+class ReqInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("t_arrival_us", ctypes.c_double),
+                ("t_admit_us", ctypes.c_double), ("t_launch_us", ctypes.c_double), ("t_done_us", ctypes.c_double),
+                ("bytes", ctypes.c_int64), ("batch_id", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("pending", ctypes.c_int64), ("max_queue", ctypes.c_int64),
+                ("max_in_use_bytes", ctypes.c_int64), ("in_use_bytes", ctypes.c_int64), ("bytes", ctypes.c_double),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("p999_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double), ("gbps", ctypes.c_double)]
+
+
+_server_sigs_done = False
+
+
+def _server_sigs():
+    global _server_sigs_done
+    if _server_sigs_done:
+        return
+    L = lib()
+    vp, st, u64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
+    L.hp_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
+    L.hp_submit.argtypes = [vp, ctypes.POINTER(Nest), vp, vp, ctypes.c_double, u64p]
+    L.hp_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ReqInfo)]
+    L.hp_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ReqInfo)]
+    L.hp_server_forget.argtypes = [vp, ctypes.c_uint64]
+    L.hp_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.hp_server_now_us.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.hp_server_replay.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Nest), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double), u64p]
+    L.hp_server_destroy.argtypes = [vp]
+    for f in ("hp_server_create", "hp_submit", "hp_poll", "hp_wait", "hp_server_forget", "hp_server_get_stats",
+              "hp_server_now_us", "hp_server_replay", "hp_server_destroy"):
+        getattr(L, f).restype = st
+    _server_sigs_done = True
+
+
+def _info(ri: ReqInfo) -> dict:
+    return {k: getattr(ri, k) for k, _ in ReqInfo._fields_ if k != "pad"}
+
+
+class Server:
+    """hp_server_*: continuous batching of nest-reduction requests."""
+
+    def __init__(self, hbm_budget=64 << 30, slot_bytes=64 << 20, streams=4, max_batch=1024, window_us=30,
+                 queue_cap=1 << 20, flags=0, fail_every_nth_batch=0):
+        _server_sigs()
+        cfg = ServerCfg(hbm_budget, slot_bytes, streams, max_batch, window_us, queue_cap, flags,
+                        fail_every_nth_batch)
+        self._h = ctypes.c_void_p()
+        check(lib().hp_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+
+    def now_us(self) -> float:
+        t = ctypes.c_double()
+        check(lib().hp_server_now_us(self._h, ctypes.byref(t)))
+        return t.value
+
+    def submit(self, extents, ops, dtype, in_ptr: int, out_ptr: int, t_arrival_us: float = -1.0) -> int:
+        n = make_nest(extents, ops, dtype)
+        t = ctypes.c_uint64()
+        check(lib().hp_submit(self._h, ctypes.byref(n), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                              t_arrival_us, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        ri = ReqInfo()
+        s = lib().hp_poll(self._h, ticket, ctypes.byref(ri))
+        if s == 7:  # HP_ENOTREADY
+            return None
+        check(s)
+        return _info(ri)
+
+    def wait(self, ticket: int) -> dict:
+        ri = ReqInfo()
+        check(lib().hp_wait(self._h, ticket, ctypes.byref(ri)))
+        return _info(ri)
+
+    def forget(self, ticket: int):
+        check(lib().hp_server_forget(self._h, ticket))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(lib().hp_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def replay(self, nests, in_ptrs, out_ptrs, t_arrival_us):
+        n = len(nests)
+        arr = (Nest * n)()
+        for i, (ext, ops, dt) in enumerate(nests):
+            arr[i] = make_nest(ext, ops, dt)
+        ins = (ctypes.c_void_p * n)(*in_ptrs)
+        outs = (ctypes.c_void_p * n)(*out_ptrs)
+        ts = (ctypes.c_double * n)(*t_arrival_us)
+        tk = (ctypes.c_uint64 * n)()
+        check(lib().hp_server_replay(self._h, n, arr, ins, outs, ts, tk))
+        return list(tk)
+
+    def close(self):
+        if self._h:
+            check(lib().hp_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,375 @@
+// Batches of nests: one persistent launch per kernel family, optionally replayed
+// from a hipGraph, and the one-launch-per-nest baseline over the same plans.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+#include "hp_nest.h"
+#include "hp_tune.h"
+
+namespace hp {
+
+hp_status batch_f32_launch(int, int, const BatchArgs&, int, int, size_t, hipStream_t);
+hp_status batch_bf16_launch(int, int, const BatchArgs&, int, int, size_t, hipStream_t);
+hp_status batch_i32_launch(int, int, const BatchArgs&, int, int, size_t, hipStream_t);
+hp_status batch_i32_deep_launch(int, int, const BatchArgs&, int, int, size_t, hipStream_t);
+int batch_f32_occupancy(int, int, int, size_t);
+int batch_bf16_occupancy(int, int, int, size_t);
+int batch_i32_occupancy(int, int, int, size_t);
+int batch_i32_deep_occupancy(int, int, int, size_t);
+
+hp_status launch_batch(int family, int chunk, const BatchArgs& B, int grid, int nw, size_t lds, hipStream_t st) {
+  switch (family) {
+    case FAM_F32_4: case FAM_F32_8: return batch_f32_launch(family, chunk, B, grid, nw, lds, st);
+    case FAM_BF16_4: case FAM_BF16_8: return batch_bf16_launch(family, chunk, B, grid, nw, lds, st);
+    case FAM_I32_FLAT: case FAM_I32_SEG: return batch_i32_launch(family, chunk, B, grid, nw, lds, st);
+    default: return batch_i32_deep_launch(family, chunk, B, grid, nw, lds, st);
+  }
+}
+
+int batch_occupancy(int family, int chunk, int nw, size_t lds) {
+  switch (family) {
+    case FAM_F32_4: case FAM_F32_8: return batch_f32_occupancy(family, chunk, nw, lds);
+    case FAM_BF16_4: case FAM_BF16_8: return batch_bf16_occupancy(family, chunk, nw, lds);
+    case FAM_I32_FLAT: case FAM_I32_SEG: return batch_i32_occupancy(family, chunk, nw, lds);
+    default: return batch_i32_deep_occupancy(family, chunk, nw, lds);
+  }
+}
+
+hp_status launch_single(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
+                        hipStream_t st) {
+  switch (P.dtype) {
+    case HP_F32: return launch_nest_f32(P, dP, in, out, ws, lds, st);
+    case HP_BF16: return launch_nest_bf16(P, dP, in, out, ws, lds, st);
+    default: return launch_nest_i32(P, dP, in, out, ws, lds, st);
+  }
+}
+
+}  // namespace hp
+
+namespace {
+
+struct Group {  // nests of one kernel family and chunk: one persistent launch
+  int family, chunk;
+  long long n_tasks;
+  int2* d_tasks;
+  unsigned int* d_ctr;
+  int grid;
+  size_t lds;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct hp_batch_s {
+  int64_t n;
+  uint32_t flags;
+  int device;
+  int nw;
+  std::vector<hp::DevPlan> plans;
+  std::vector<hp_plan_info> infos;
+  hp::DevPlan* d_plans = nullptr;
+  const void** d_in = nullptr;
+  void** d_out = nullptr;
+  unsigned char** d_ws = nullptr;
+  std::vector<unsigned char*> ws_ptrs;
+  void* arena = nullptr;  // tasks, counters, workspaces
+  std::vector<Group> groups;
+  bool io_set = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_each = nullptr;
+  hipGraphExec_t exec_each = nullptr;
+  double bytes = 0;
+};
+
+static void batch_free(hp_batch_s* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec_each) (void)hipGraphExecDestroy(b->exec_each);
+  if (b->graph_each) (void)hipGraphDestroy(b->graph_each);
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->d_plans) (void)hipFree(b->d_plans);
+  if (b->d_in) (void)hipFree(b->d_in);
+  delete b;
+}
+
+extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t flags, hp_batch_t* out) {
+  using namespace hp;
+  if (!out || !nests || n < 1) return fail(HP_EINVAL, "null argument or empty batch");
+  *out = nullptr;
+  if (flags & ~(uint32_t)(HP_BATCH_GRAPH | HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL | HP_BATCH_NO_TUNE))
+    return fail(HP_EINVAL, "unknown batch flag bits 0x%x", flags);
+  hp_batch_s* b = new (std::nothrow) hp_batch_s;
+  if (!b) return fail(HP_ENOMEM, "host allocation failed");
+  b->n = n;
+  b->flags = flags;
+  b->nw = kBatchWaves;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    batch_free(b);
+    return fail(HP_EDEVICE, "no HIP device");
+  }
+  b->plans.resize((size_t)n);
+  b->infos.resize((size_t)n);
+  const uint32_t pflags = flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL);
+  for (int64_t i = 0; i < n; ++i) {
+    Lowered L;
+    hp_status s = plan_for_batch(&nests[i], pflags, !(flags & HP_BATCH_NO_TUNE), b->nw, &L);
+    if (s != HP_OK) {
+      batch_free(b);
+      char msg[512];
+      snprintf(msg, sizeof msg, "%s", hp_last_error());
+      return fail(s, "nest %lld: %s", (long long)i, msg);
+    }
+    b->plans[(size_t)i] = L.dp;
+    b->infos[(size_t)i] = L.info;
+    b->bytes += (double)L.info.in_bytes + (double)L.info.out_bytes;
+  }
+  // groups by (family, chunk); tasks largest first inside a group
+  std::vector<std::vector<int64_t>> members;
+  std::vector<std::pair<int, int>> keys;
+  for (int64_t i = 0; i < n; ++i) {
+    const DevPlan& P = b->plans[(size_t)i];
+    std::pair<int, int> k(family_of(P), P.chunk);
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != k) ++g;
+    if (g == keys.size()) {
+      keys.push_back(k);
+      members.emplace_back();
+    }
+    members[g].push_back(i);
+  }
+  // device memory: plans, pointer tables, then one arena for tasks, counters and workspaces
+  size_t arena_bytes = 0;
+  std::vector<size_t> task_off(keys.size()), ctr_off(keys.size());
+  std::vector<long long> ntask(keys.size(), 0);
+  for (size_t g = 0; g < keys.size(); ++g) {
+    for (int64_t i : members[g]) ntask[g] += b->plans[(size_t)i].grid;
+    task_off[g] = arena_bytes;
+    arena_bytes = align_up(arena_bytes + (size_t)ntask[g] * sizeof(int2), 256);
+    ctr_off[g] = arena_bytes;
+    arena_bytes = align_up(arena_bytes + 2 * sizeof(unsigned int), 256);
+  }
+  std::vector<size_t> ws_off((size_t)n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const size_t wb = b->infos[(size_t)i].workspace_bytes;
+    if (wb) {
+      ws_off[(size_t)i] = arena_bytes;
+      arena_bytes = align_up(arena_bytes + wb, 256);
+    }
+  }
+  if (hipMalloc(&b->d_plans, sizeof(DevPlan) * (size_t)n) != hipSuccess ||
+      hipMalloc((void**)&b->d_in, 3 * sizeof(void*) * (size_t)n) != hipSuccess ||
+      hipMalloc(&b->arena, arena_bytes) != hipSuccess) {
+    batch_free(b);
+    return fail(HP_ENOMEM, "batch device allocation failed");
+  }
+  b->d_out = reinterpret_cast<void**>(const_cast<void**>(b->d_in + n));
+  b->d_ws = reinterpret_cast<unsigned char**>(const_cast<void**>(b->d_in + 2 * n));
+  std::vector<unsigned char> host_arena(arena_bytes, 0);
+  b->ws_ptrs.assign((size_t)n, nullptr);
+  for (int64_t i = 0; i < n; ++i)
+    if (b->infos[(size_t)i].workspace_bytes) b->ws_ptrs[(size_t)i] = (unsigned char*)b->arena + ws_off[(size_t)i];
+  for (size_t g = 0; g < keys.size(); ++g) {
+    std::vector<int64_t>& mem = members[g];
+    // largest work per task first
+    std::stable_sort(mem.begin(), mem.end(), [&](int64_t a, int64_t c) {
+      const double wa = (double)b->infos[(size_t)a].in_bytes / (double)b->plans[(size_t)a].grid;
+      const double wc = (double)b->infos[(size_t)c].in_bytes / (double)b->plans[(size_t)c].grid;
+      return wa > wc;
+    });
+    int2* t = reinterpret_cast<int2*>(host_arena.data() + task_off[g]);
+    long long k = 0;
+    for (int64_t i : mem)
+      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w) t[k++] = make_int2((int)i, (int)w);
+    Group G;
+    G.family = keys[g].first;
+    G.chunk = keys[g].second;
+    G.n_tasks = ntask[g];
+    G.d_tasks = reinterpret_cast<int2*>((unsigned char*)b->arena + task_off[g]);
+    G.d_ctr = reinterpret_cast<unsigned int*>((unsigned char*)b->arena + ctr_off[g]);
+    G.lds = 16;
+    for (int64_t i : mem) G.lds = std::max(G.lds, b->infos[(size_t)i].lds_bytes);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
+      cus = 256;
+    int occ = batch_occupancy(G.family, G.chunk, b->nw, G.lds);
+    if (occ < 1) occ = 1;
+    long long grid = (long long)cus * occ;
+    if (grid > G.n_tasks) grid = G.n_tasks;
+    G.grid = (int)grid;
+    b->groups.push_back(G);
+  }
+  std::vector<unsigned char*> wsv(b->ws_ptrs);
+  if (hipMemcpy(b->d_plans, b->plans.data(), sizeof(DevPlan) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->arena, host_arena.data(), arena_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_ws, wsv.data(), sizeof(void*) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(b->d_in, 0, 2 * sizeof(void*) * (size_t)n) != hipSuccess) {
+    batch_free(b);
+    return fail(HP_EDEVICE, "batch upload failed");
+  }
+  *out = b;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_info(hp_batch_t b, int64_t i, hp_plan_info* info) {
+  if (!b || !info || i < 0 || i >= b->n) return hp::fail(HP_EINVAL, "bad batch, index or info pointer");
+  *info = b->infos[(size_t)i];
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_stats(hp_batch_t b, int64_t* n_launches, int64_t* n_tasks, double* bytes) {
+  if (!b) return hp::fail(HP_EINVAL, "null batch");
+  long long t = 0;
+  for (const Group& g : b->groups) t += g.n_tasks;
+  if (n_launches) *n_launches = (int64_t)b->groups.size();
+  if (n_tasks) *n_tasks = t;
+  if (bytes) *bytes = b->bytes;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_set_io(hp_batch_t b, const void* const* d_in, void* const* d_out) {
+  if (!b || !d_in || !d_out) return hp::fail(HP_EINVAL, "null argument");
+  for (int64_t i = 0; i < b->n; ++i) {
+    if (!d_in[i] || !d_out[i]) return hp::fail(HP_EINVAL, "nest %lld: null pointer", (long long)i);
+    if (reinterpret_cast<uintptr_t>(d_in[i]) & 15u)
+      return hp::fail(HP_EINVAL, "nest %lld: input not 16-byte aligned", (long long)i);
+    const int od = b->infos[(size_t)i].out_dtype;
+    const uintptr_t al = (od == HP_I64 || od == HP_F64) ? 7u : 3u;
+    if (reinterpret_cast<uintptr_t>(d_out[i]) & al)
+      return hp::fail(HP_EINVAL, "nest %lld: output misaligned", (long long)i);
+  }
+  if (b->exec_each) {  // that graph holds the old pointers as launch arguments
+    (void)hipGraphExecDestroy(b->exec_each);
+    (void)hipGraphDestroy(b->graph_each);
+    b->exec_each = nullptr;
+    b->graph_each = nullptr;
+  }
+  if (hipMemcpy(b->d_in, d_in, sizeof(void*) * (size_t)b->n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_out, d_out, sizeof(void*) * (size_t)b->n, hipMemcpyHostToDevice) != hipSuccess)
+    return hp::fail(HP_EDEVICE, "pointer table upload failed");
+  b->io_set = true;
+  return HP_OK;
+}
+
+static hp_status launch_groups(hp_batch_s* b, hipStream_t st) {
+  for (const Group& G : b->groups) {
+    hp::BatchArgs A;
+    A.plans = b->d_plans;
+    A.tasks = G.d_tasks;
+    A.n_tasks = G.n_tasks;
+    A.ctr = G.d_ctr;
+    A.ins = b->d_in;
+    A.outs = b->d_out;
+    A.wss = b->d_ws;
+    hp_status s = hp::launch_batch(G.family, G.chunk, A, G.grid, b->nw, G.lds, st);
+    if (s != HP_OK) return s;
+  }
+  return HP_OK;
+}
+
+static hp_status capture(hp_batch_s* b, bool each, hipGraph_t* graph, hipGraphExec_t* exec);
+
+extern "C" hp_status hp_batch_run(hp_batch_t b, void* stream) {
+  if (!b) return hp::fail(HP_EINVAL, "null batch");
+  if (!b->io_set) return hp::fail(HP_ESTATE, "hp_batch_set_io has not been called");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+    return hp::fail(HP_EINVAL, "batch was made on device %d, current device is %d", b->device, dev);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (b->flags & HP_BATCH_GRAPH) {
+    if (!b->exec) {
+      hp_status s = capture(b, false, &b->graph, &b->exec);
+      if (s != HP_OK) return s;
+    }
+    if (hipGraphLaunch(b->exec, st) != hipSuccess) return hp::fail(HP_EDEVICE, "graph launch failed");
+    return HP_OK;
+  }
+  return launch_groups(b, st);
+}
+
+// Baseline: the same plans, one single-nest launch per nest (optionally replayed
+// from one graph holding all of those launches).
+static hp_status launch_each(hp_batch_s* b, hipStream_t st) {
+  std::vector<const void*> in((size_t)b->n);
+  std::vector<void*> out((size_t)b->n);
+  if (hipMemcpy(in.data(), b->d_in, sizeof(void*) * (size_t)b->n, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(out.data(), b->d_out, sizeof(void*) * (size_t)b->n, hipMemcpyDeviceToHost) != hipSuccess)
+    return hp::fail(HP_EDEVICE, "pointer table download failed");
+  for (int64_t i = 0; i < b->n; ++i) {
+    hp_status s = hp::launch_single(b->plans[(size_t)i], b->d_plans + i, in[(size_t)i], out[(size_t)i],
+                                    b->ws_ptrs[(size_t)i], b->infos[(size_t)i].lds_bytes, st);
+    if (s != HP_OK) return s;
+  }
+  return HP_OK;
+}
+
+static hp_status capture(hp_batch_s* b, bool each, hipGraph_t* graph, hipGraphExec_t* exec) {
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return hp::fail(HP_EDEVICE, "capture stream creation failed");
+  hp_status s = HP_OK;
+  if (each) {
+    // the host-side pointer copies must not be captured: fetch them first
+    std::vector<const void*> ins((size_t)b->n);
+    std::vector<void*> outs((size_t)b->n);
+    if (hipMemcpy(ins.data(), b->d_in, sizeof(void*) * (size_t)b->n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(outs.data(), b->d_out, sizeof(void*) * (size_t)b->n, hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hp::fail(HP_EDEVICE, "pointer table download failed");
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hp::fail(HP_EDEVICE, "begin capture failed");
+    }
+    for (int64_t i = 0; i < b->n && s == HP_OK; ++i)
+      s = hp::launch_single(b->plans[(size_t)i], b->d_plans + i, ins[(size_t)i], outs[(size_t)i],
+                            b->ws_ptrs[(size_t)i], b->infos[(size_t)i].lds_bytes, cs);
+  } else {
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hp::fail(HP_EDEVICE, "begin capture failed");
+    }
+    s = launch_groups(b, cs);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (s != HP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess || !g) return hp::fail(HP_EDEVICE, "end capture failed");
+  if (hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hp::fail(HP_EDEVICE, "graph instantiation failed");
+  }
+  *graph = g;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_run_each(hp_batch_t b, void* stream, int32_t use_graph) {
+  if (!b) return hp::fail(HP_EINVAL, "null batch");
+  if (!b->io_set) return hp::fail(HP_ESTATE, "hp_batch_set_io has not been called");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (use_graph) {
+    if (!b->exec_each) {
+      hp_status s = capture(b, true, &b->graph_each, &b->exec_each);
+      if (s != HP_OK) return s;
+    }
+    if (hipGraphLaunch(b->exec_each, st) != hipSuccess) return hp::fail(HP_EDEVICE, "graph launch failed");
+    return HP_OK;
+  }
+  return launch_each(b, st);
+}
+
+extern "C" hp_status hp_batch_destroy(hp_batch_t b) {
+  batch_free(b);
+  return HP_OK;
+}

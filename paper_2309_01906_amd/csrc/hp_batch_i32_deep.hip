@@ -1,0 +1,46 @@
+// Persistent batched kernels: int32 nests of any depth and segment count.
+#include "hp_nest.h"
+
+namespace hp {
+
+__global__ void __launch_bounds__(1024) k_batch_i32_deep_0(const BatchArgs B) {
+  extern __shared__ __align__(16) char lds[];
+  batch_run<IntT, 4, kMaxDepth, 8, kMaxDepth>(B, lds);
+}
+
+__global__ void __launch_bounds__(1024) k_batch_i32_deep_1(const BatchArgs B) {
+  extern __shared__ __align__(16) char lds[];
+  batch_run<IntT, 1, kMaxDepth, 16, kMaxDepth>(B, lds);
+}
+
+static hp_status launch_check() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HP_EDEVICE, "batch kernel launch failed: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+hp_status batch_i32_deep_launch(int family, int chunk, const BatchArgs& B, int grid, int nw, size_t lds, hipStream_t st) {
+  if (family == FAM_I32_DEEP && chunk == 4) {
+    hipLaunchKernelGGL(k_batch_i32_deep_0, dim3((unsigned)grid), dim3((unsigned)(nw * kWave)), lds, st, B);
+    return launch_check();
+  }
+  if (family == FAM_I32_DEEP && chunk == 1) {
+    hipLaunchKernelGGL(k_batch_i32_deep_1, dim3((unsigned)grid), dim3((unsigned)(nw * kWave)), lds, st, B);
+    return launch_check();
+  }
+  return fail(HP_EUNSUPPORTED, "no batch kernel for family %d chunk %d", family, chunk);
+}
+int batch_i32_deep_occupancy(int family, int chunk, int nw, size_t lds) {
+  int nb = 0;
+  if (family == FAM_I32_DEEP && chunk == 4) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_i32_deep_0, nw * kWave, lds) != hipSuccess) return 0;
+    return nb;
+  }
+  if (family == FAM_I32_DEEP && chunk == 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_i32_deep_1, nw * kWave, lds) != hipSuccess) return 0;
+    return nb;
+  }
+  return 0;
+}
+
+}  // namespace hp

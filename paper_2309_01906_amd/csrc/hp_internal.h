@@ -98,7 +98,9 @@ struct Lowered {
 };
 
 // Fill `out` from nest + map; sets the thread-local error text on failure.
-hp_status lower(const hp_nest* nest, const hp_level_map* map, uint32_t flags, Lowered* out);
+// force_nw > 0 (batched plans): the plan must use exactly that many waves per
+// workgroup; the automatic map gives them to its wave level.
+hp_status lower(const hp_nest* nest, const hp_level_map* map, uint32_t flags, Lowered* out, int force_nw = 0);
 
 // Thread-local error text.
 hp_status fail(hp_status s, const char* fmt, ...);

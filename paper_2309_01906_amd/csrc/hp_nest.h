@@ -857,6 +857,62 @@ __device__ __forceinline__ uint32_t logical_group(const DevPlan& P, uint32_t b) 
   return (b & 7u) * per + (b >> 3);
 }
 
+// Persistent batched kernel body: workgroups pop (nest, workgroup) tasks from one
+// atomic counter (a dynamic schedule on the grid level, which needs exactly this one
+// synchronisation point) and run that nest's plan for that workgroup.  Tasks are
+// ordered largest first.  The last workgroup to leave resets the counters, so the
+// launch can be replayed (e.g. from a hipGraph) without clearing memory.
+struct BatchArgs {
+  const DevPlan* plans;        // one plan per nest
+  const int2* tasks;           // (nest, logical workgroup), largest first
+  long long n_tasks;
+  unsigned int* ctr;           // [0] next task, [1] workgroups finished
+  const void* const* ins;      // per nest
+  void* const* outs;           // per nest
+  unsigned char* const* wss;   // per nest (grid-combine workspace, may be null)
+};
+
+template <class T, int C, int NS, int U, int KD>
+__device__ __forceinline__ void batch_run(const BatchArgs& B, char* lds) {
+  __shared__ long long s_task;
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_task = (long long)__hip_atomic_fetch_add(&B.ctr[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const long long t = s_task;
+    __syncthreads();
+    if (t >= B.n_tasks) break;
+    const int2 te = B.tasks[t];
+    wg_run<T, C, NS, U, KD>(B.plans[te.x], reinterpret_cast<const typename T::Raw*>(B.ins[te.x]), B.outs[te.x],
+                            B.wss[te.x], (uint32_t)te.y, lds);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const unsigned int done = __hip_atomic_fetch_add(&B.ctr[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(&B.ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&B.ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Kernel families.  Every nest of one persistent launch belongs to one family.
+enum Family : int32_t {
+  FAM_F32_4 = 0, FAM_F32_8, FAM_BF16_4, FAM_BF16_8, FAM_I32_FLAT, FAM_I32_SEG, FAM_I32_DEEP, FAM_COUNT
+};
+__host__ __device__ inline int family_of(const DevPlan& P) {
+  if (P.dtype == HP_F32) return P.depth <= 4 ? FAM_F32_4 : FAM_F32_8;
+  if (P.dtype == HP_BF16) return P.depth <= 4 ? FAM_BF16_4 : FAM_BF16_8;
+  if (P.depth <= 4 && P.nseg <= 1) return FAM_I32_FLAT;
+  if (P.depth <= 4 && P.nseg <= 3) return FAM_I32_SEG;
+  return FAM_I32_DEEP;
+}
+
+// Launch a persistent batch of one family / chunk on `grid` workgroups of nw waves.
+hp_status launch_batch(int family, int chunk, const BatchArgs& B, int grid, int nw, size_t lds, hipStream_t st);
+// Resident workgroups per CU for that kernel.
+int batch_occupancy(int family, int chunk, int nw, size_t lds);
+
 // Launchers, one per input type (each in its own translation unit).  P is the host
 // copy (launch geometry), dP the same plan in device memory (read by the kernel).
 hp_status launch_nest_f32(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,

@@ -52,11 +52,17 @@ static int elem_bytes(int dt) { return dt == HP_BF16 ? 2 : 4; }
 // then the waves of a workgroup (LDS + barrier), then, when the outputs alone do
 // not give the chip enough workgroups, the outermost reducing level is also split
 // over the grid (atomic ticket combine).
-static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m) {
+static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, int force_nw) {
   const int d = n->depth;
   memset(m, 0, sizeof *m);
   for (int l = 0; l < p; ++l) m->scopes[l] = HP_SCOPE_G;
-  if (p == d) return;
+  if (p == d) {
+    if (force_nw > 1) {  // a copy in a batch: the innermost level also takes the waves
+      m->scopes[d - 1] = HP_SCOPE_G | HP_SCOPE_W;
+      m->units[d - 1][HP_AXIS_W] = (uint32_t)force_nw;
+    }
+    return;
+  }
   // lanes of one wavefront, innermost reducing level first
   int lanes_left = kWave;
   int l = d - 1;
@@ -93,6 +99,7 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m) {
   {
     uint64_t f = pow2ceil((uint64_t)per_wave_unit);
     if (f > nw_target) f = nw_target;
+    if (force_nw > 0) f = (uint64_t)force_nw;
     m->units[w_level][HP_AXIS_W] = (uint32_t)f;
   }
   // anything further out runs on the grid, one workgroup per iteration
@@ -119,7 +126,7 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m) {
   }
 }
 
-hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out) {
+hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw) {
   if (!n || !out) return fail(HP_EINVAL, "null argument");
   if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_TEMPORAL))
     return fail(HP_EINVAL, "unknown flag bits 0x%x", flags);
@@ -156,7 +163,7 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
   if (map_in) {
     m = *map_in;
   } else {
-    auto_map(n, p, chunk_last, &m);
+    auto_map(n, p, chunk_last, &m, force_nw);
   }
   // ---- validate the map
   for (int l = 0; l < d; ++l) {
@@ -263,6 +270,8 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
       }
     dp.nw = 1 << sh;
     if (dp.nw > kMaxWaves) return fail(HP_EINVAL, "more than %d waves per workgroup", kMaxWaves);
+    if (force_nw > 0 && dp.nw != force_nw)
+      return fail(HP_EUNSUPPORTED, "batched plans use %d waves per workgroup, this map gives %d", force_nw, dp.nw);
     dp.idle_wmask = 0;
   }
   // ---- segments of reducing levels

@@ -1,0 +1,313 @@
+// Autotuner: picks, per size class, how the reduced block of a single-segment nest
+// is split between the grid, the waves and the lanes (and how it is viewed as
+// (J, K) rows), by timing candidate plans on the device.  The paper's section 3.9
+// selects kernel versions per hardware; here the versions are level maps of one
+// kernel, chosen by measurement on the gfx950 at hand and kept in a cache file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+#include "hp_nest.h"
+#include "hp_tune.h"
+
+namespace hp {
+hp_status launch_single(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
+                        hipStream_t st);
+}
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, hp::Recipe> g_cache;
+bool g_env_loaded = false;
+
+int lb(int64_t x) {
+  int r = 0;
+  while ((int64_t(1) << (r + 1)) <= x) ++r;
+  return r;
+}
+
+int elem_bytes(int dt) { return dt == HP_BF16 ? 2 : 4; }
+
+// one segment of SUM, MIN or MAX: the block is one flat reduction and may be reshaped
+bool single_segment(const hp_nest* n, int* p_out, int64_t* block) {
+  int p = n->depth;
+  for (int l = 0; l < n->depth; ++l)
+    if (n->op[l] != HP_OP_NONE) {
+      p = l;
+      break;
+    }
+  if (p == n->depth) return false;
+  const int op = n->op[p];
+  if (op == HP_OP_ARGMIN || op == HP_OP_ARGMAX) return false;
+  int64_t b = 1;
+  for (int l = p; l < n->depth; ++l) {
+    if (n->op[l] != op) return false;
+    b *= n->extent[l];
+  }
+  *p_out = p;
+  *block = b;
+  return true;
+}
+
+hp_status load_file_locked(const char* path) {
+  FILE* f = fopen(path, "r");
+  if (!f) return hp::fail(HP_EINVAL, "cannot open tuner cache %s", path);
+  char key[256];
+  long long k;
+  int vj, gj;
+  double us;
+  while (fscanf(f, "%255s %lld %d %d %lf", key, &k, &vj, &gj, &us) == 5) g_cache[key] = hp::Recipe{k, vj, gj, us};
+  fclose(f);
+  return HP_OK;
+}
+
+void load_env_locked() {
+  if (g_env_loaded) return;
+  g_env_loaded = true;
+  const char* p = getenv("HP_TUNE_CACHE");
+  if (p && *p) (void)load_file_locked(p);
+}
+
+}  // namespace
+
+namespace hp {
+
+std::string tune_key(const hp_nest* n) {
+  int p = 0;
+  int64_t block = 1, outs = 1;
+  char ops[HP_MAX_DEPTH + 1] = {0};
+  for (int l = 0; l < n->depth; ++l) {
+    ops[l] = "NSmMaA"[n->op[l] < 6 && n->op[l] >= 0 ? n->op[l] : 0];
+    if (n->op[l] == HP_OP_NONE) {
+      outs *= n->extent[l];
+      ++p;
+    } else {
+      block *= n->extent[l];
+    }
+  }
+  char buf[96];
+  snprintf(buf, sizeof buf, "gfx950:%d:%s:o%d:b%d", n->dtype, ops, lb(outs), lb(block));
+  return buf;
+}
+
+bool apply_recipe(const hp_nest* n, const Recipe& r, int nw, hp_nest* shaped, hp_level_map* map) {
+  int p;
+  int64_t block;
+  if (r.k <= 0 || !single_segment(n, &p, &block)) return false;
+  if (block % r.k != 0 || p + 2 > HP_MAX_DEPTH) return false;
+  if (r.vj < 1 || r.vj > 64 || (r.vj & (r.vj - 1)) || r.gj < 1) return false;
+  const int op = n->op[p];
+  memset(shaped, 0, sizeof *shaped);
+  shaped->dtype = n->dtype;
+  for (int l = 0; l < p; ++l) {
+    shaped->extent[l] = n->extent[l];
+    shaped->op[l] = HP_OP_NONE;
+  }
+  shaped->extent[p] = block / r.k;
+  shaped->op[p] = op;
+  shaped->extent[p + 1] = r.k;
+  shaped->op[p + 1] = op;
+  shaped->depth = p + 2;
+  memset(map, 0, sizeof *map);
+  for (int l = 0; l < p; ++l) map->scopes[l] = HP_SCOPE_G;
+  uint32_t sj = HP_SCOPE_W;
+  if (r.gj > 1) sj |= HP_SCOPE_G;
+  if (r.vj > 1) sj |= HP_SCOPE_V;
+  map->scopes[p] = sj;
+  map->units[p][HP_AXIS_W] = (uint32_t)nw;
+  if (r.gj > 1) map->units[p][HP_AXIS_G] = (uint32_t)r.gj;
+  if (r.vj > 1) map->units[p][HP_AXIS_V] = (uint32_t)r.vj;
+  map->scopes[p + 1] = HP_SCOPE_V;
+  map->units[p + 1][HP_AXIS_V] = (uint32_t)(64 / r.vj);
+  return true;
+}
+
+hp_status plan_for_batch(const hp_nest* nest, uint32_t flags, bool use_tuner, int nw, Lowered* out) {
+  if (!nest) return fail(HP_EINVAL, "null nest");
+  if (use_tuner) {
+    Recipe r{0, 1, 1, 0.0};
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      load_env_locked();
+      auto it = g_cache.find(tune_key(nest));
+      if (it != g_cache.end()) {
+        r = it->second;
+        have = true;
+      }
+    }
+    hp_nest shaped;
+    hp_level_map m;
+    if (have && apply_recipe(nest, r, nw, &shaped, &m)) {
+      if (lower(&shaped, &m, flags, out, nw) == HP_OK) return HP_OK;
+    }
+  }
+  return lower(nest, nullptr, flags, out, nw);
+}
+
+}  // namespace hp
+
+// ---------------------------------------------------------------------------
+// C API
+
+extern "C" hp_status hp_tune_cache_load(const char* path) {
+  if (!path) return hp::fail(HP_EINVAL, "null path");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_env_loaded = true;
+  return load_file_locked(path);
+}
+
+extern "C" hp_status hp_tune_cache_save(const char* path) {
+  if (!path) return hp::fail(HP_EINVAL, "null path");
+  std::lock_guard<std::mutex> lk(g_mu);
+  FILE* f = fopen(path, "w");
+  if (!f) return hp::fail(HP_EINVAL, "cannot write %s", path);
+  for (const auto& kv : g_cache)
+    fprintf(f, "%s %lld %d %d %.3f\n", kv.first.c_str(), (long long)kv.second.k, kv.second.vj, kv.second.gj,
+            kv.second.us);
+  fclose(f);
+  return HP_OK;
+}
+
+extern "C" hp_status hp_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+  g_env_loaded = true;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_tune_cache_size(int64_t* n) {
+  if (!n) return hp::fail(HP_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(g_mu);
+  *n = (int64_t)g_cache.size();
+  return HP_OK;
+}
+
+namespace {
+
+struct Timed {
+  hp::Recipe r;
+  double us;
+};
+
+// median device time of `reps` runs of one candidate plan (single-nest kernel)
+hp_status time_candidate(const hp::Lowered& L, const void* in, void* out, int reps, hipStream_t st, double* us) {
+  hp::DevPlan* dP = nullptr;
+  void* ws = nullptr;
+  hipEvent_t e0, e1;
+  if (hipMalloc(&dP, sizeof(hp::DevPlan)) != hipSuccess) return hp::fail(HP_ENOMEM, "tuner plan allocation");
+  if (hipMemcpy(dP, &L.dp, sizeof(hp::DevPlan), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dP);
+    return hp::fail(HP_EDEVICE, "tuner plan upload");
+  }
+  if (L.info.workspace_bytes) {
+    if (hipMalloc(&ws, L.info.workspace_bytes) != hipSuccess ||
+        hipMemset(ws, 0, L.info.workspace_bytes) != hipSuccess) {
+      (void)hipFree(dP);
+      if (ws) (void)hipFree(ws);
+      return hp::fail(HP_ENOMEM, "tuner workspace allocation");
+    }
+  }
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  std::vector<float> t;
+  hp_status s = HP_OK;
+  for (int r = 0; r < reps + 2 && s == HP_OK; ++r) {
+    (void)hipEventRecord(e0, st);
+    s = hp::launch_single(L.dp, dP, in, out, ws, L.info.lds_bytes, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) s = hp::fail(HP_EDEVICE, "tuner run failed");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (r >= 2) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(dP);
+  if (ws) (void)hipFree(ws);
+  if (s != HP_OK) return s;
+  std::sort(t.begin(), t.end());
+  *us = t.empty() ? 0.0 : 1e3 * (double)t[t.size() / 2];
+  return HP_OK;
+}
+
+}  // namespace
+
+extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t reps, double* best_us,
+                                  double* auto_us) {
+  using namespace hp;
+  if (!nest || reps < 1) return fail(HP_EINVAL, "bad argument");
+  int p;
+  int64_t block;
+  Lowered L0;
+  hp_status s = lower(nest, nullptr, flags, &L0, kBatchWaves);
+  if (s != HP_OK) return s;
+  const bool tunable = single_segment(nest, &p, &block);
+  // device buffers of the nest's size (values do not change the kernels' timing)
+  void* in = nullptr;
+  void* out = nullptr;
+  if (hipMalloc(&in, L0.info.in_bytes + 16) != hipSuccess) return fail(HP_ENOMEM, "tuner input allocation");
+  if (hipMemset(in, 0, L0.info.in_bytes + 16) != hipSuccess || hipMalloc(&out, L0.info.out_bytes + 16) != hipSuccess) {
+    (void)hipFree(in);
+    return fail(HP_ENOMEM, "tuner output allocation");
+  }
+  hipStream_t st;
+  if (hipStreamCreate(&st) != hipSuccess) {
+    (void)hipFree(in);
+    (void)hipFree(out);
+    return fail(HP_EDEVICE, "tuner stream");
+  }
+  double t_auto = 0;
+  s = time_candidate(L0, in, out, reps, st, &t_auto);
+  Recipe best{0, 1, 1, t_auto};
+  if (s == HP_OK && tunable) {
+    const int c = 16 / elem_bytes(nest->dtype);
+    std::vector<int64_t> ks;
+    for (int64_t k = c; k <= block && k <= (int64_t)c * 1024; k *= 2)
+      if (block % k == 0) ks.push_back(k);
+    int64_t outs = 1;
+    for (int l = 0; l < p; ++l) outs *= nest->extent[l];
+    for (int64_t k : ks) {
+      for (int vj = 1; vj <= 16; vj *= 2) {
+        if ((64 / vj) * c > 4 * k) continue;  // most lanes of a row would idle
+        const int64_t J = block / k;
+        if (vj > J) continue;
+        for (int gj = 1; gj <= 512; gj *= 2) {
+          if ((int64_t)gj * kBatchWaves * vj > J) break;
+          if (outs * gj > 65536) break;
+          Recipe r{k, vj, gj, 0.0};
+          hp_nest shaped;
+          hp_level_map m;
+          Lowered L;
+          if (!apply_recipe(nest, r, kBatchWaves, &shaped, &m)) continue;
+          if (lower(&shaped, &m, flags, &L, kBatchWaves) != HP_OK) continue;
+          double us = 0;
+          if (time_candidate(L, in, out, reps, st, &us) != HP_OK) continue;
+          if (us < best.us * 0.98) {
+            best = r;
+            best.us = us;
+          }
+        }
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_env_locked();
+    g_cache[tune_key(nest)] = best;
+  }
+  (void)hipStreamDestroy(st);
+  (void)hipFree(in);
+  (void)hipFree(out);
+  if (s != HP_OK) return s;
+  if (best_us) *best_us = best.us;
+  if (auto_us) *auto_us = t_auto;
+  return HP_OK;
+}
