@@ -101,6 +101,7 @@ typedef struct hp_level_map {
 #define HP_FLAG_SCALAR 0x2u    /* one element per load on the innermost level */
 #define HP_FLAG_NO_XCD 0x4u    /* no XCD-contiguous workgroup renumbering */
 #define HP_FLAG_TEMPORAL 0x8u  /* plain (cached) loads instead of nontemporal ones */
+#define HP_FLAG_GENERIC 0x10u  /* always use the general kernel (no lean streaming variant) */
 
 /* What the planner decided; filled by hp_plan_inspect / hp_plan_info. */
 typedef struct hp_plan_info {

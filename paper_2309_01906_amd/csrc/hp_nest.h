@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hp_internal.h"
 
 namespace hp {
@@ -429,7 +431,7 @@ __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typena
   return a;
 }
 
-template <class T, int C, int OP, int U, int KD>
+template <class T, int C, int OP, int U, int KD, bool LEAN>
 __device__ __forceinline__ typename T::Acc stream_any(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                                       long long base, bool valid, const Thread<KD>& th) {
   // every lane of the wave valid and no ragged level: no masking needed
@@ -438,7 +440,7 @@ __device__ __forceinline__ typename T::Acc stream_any(const DevPlan& P, const ty
   for (int k = 0; k < KD; ++k)
     if (k < P.nid && P.id_ragged[k]) rag = true;
   const bool check = rag || __builtin_amdgcn_ballot_w64(!valid) != 0;
-  if (P.nid <= 1) {
+  if (LEAN || P.nid <= 1) {  // lean kernels are only launched for plans with nid <= 1
     if (check) return stream<T, C, OP, U, 1, KD, true>(P, in, base, valid, th);
     return stream<T, C, OP, U, 1, KD, false>(P, in, base, valid, th);
   }
@@ -449,25 +451,25 @@ __device__ __forceinline__ typename T::Acc stream_any(const DevPlan& P, const ty
   return stream<T, C, OP, U, KD, KD, true>(P, in, base, valid, th);
 }
 
-template <class T, int C, int U, int KD>
+template <class T, int C, int U, int KD, bool LEAN>
 struct InnerStream;
-template <class R, int C, int U, int KD>
-struct InnerStream<FloatT<R>, C, U, KD> {
+template <class R, int C, int U, int KD, bool LEAN>
+struct InnerStream<FloatT<R>, C, U, KD, LEAN> {
   __device__ static __forceinline__ FAcc run(const DevPlan& P, const R* __restrict__ in, long long base, bool valid,
                                              const Thread<KD>& th) {
-    return stream_any<FloatT<R>, C, HP_OP_SUM, U, KD>(P, in, base, valid, th);
+    return stream_any<FloatT<R>, C, HP_OP_SUM, U, KD, LEAN>(P, in, base, valid, th);
   }
 };
-template <int C, int U, int KD>
-struct InnerStream<IntT, C, U, KD> {
+template <int C, int U, int KD, bool LEAN>
+struct InnerStream<IntT, C, U, KD, LEAN> {
   __device__ static __forceinline__ IAcc run(const DevPlan& P, const int32_t* __restrict__ in, long long base,
                                              bool valid, const Thread<KD>& th) {
     switch (P.seg[P.nseg - 1].op) {
-      case HP_OP_MIN: return stream_any<IntT, C, HP_OP_MIN, U, KD>(P, in, base, valid, th);
-      case HP_OP_MAX: return stream_any<IntT, C, HP_OP_MAX, U, KD>(P, in, base, valid, th);
-      case HP_OP_ARGMIN: return stream_any<IntT, C, HP_OP_ARGMIN, U, KD>(P, in, base, valid, th);
-      case HP_OP_ARGMAX: return stream_any<IntT, C, HP_OP_ARGMAX, U, KD>(P, in, base, valid, th);
-      default: return stream_any<IntT, C, HP_OP_SUM, U, KD>(P, in, base, valid, th);
+      case HP_OP_MIN: return stream_any<IntT, C, HP_OP_MIN, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_MAX: return stream_any<IntT, C, HP_OP_MAX, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_ARGMIN: return stream_any<IntT, C, HP_OP_ARGMIN, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_ARGMAX: return stream_any<IntT, C, HP_OP_ARGMAX, U, KD, LEAN>(P, in, base, valid, th);
+      default: return stream_any<IntT, C, HP_OP_SUM, U, KD, LEAN>(P, in, base, valid, th);
     }
   }
 };
@@ -496,7 +498,7 @@ __device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const D
 
 // Reduce the current output's block; returns segment P.gq's value (the output, or
 // this workgroup's partial of it when that segment spans workgroups).
-template <class T, int C, int NS, int U, int KD>
+template <class T, int C, int NS, int U, int KD, bool LEAN>
 __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                                         long long base, bool vnone, const Thread<KD>& th, char* lds) {
   using Acc = typename T::Acc;
@@ -517,18 +519,37 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
 #pragma unroll
   for (int m = 0; m < KD; ++m)
     if (m >= a_lv && m < P.depth && P.lv[m].strips == 1 && P.lv[m].ragged) inner_ok = inner_ok && th.lim[m] > 0;
-  for (long long q = 0; q < P.outer_iters; ++q) {
+  auto outer_valid = [&]() -> bool {
     bool vo = vnone && inner_ok;
 #pragma unroll
     for (int m = 0; m < KD; ++m)
       if (m >= p && m < a_lv && P.lv[m].ragged) vo = vo && (s[m] < th.lim[m]);
-    Acc ai = InnerStream<T, C, U, KD>::run(P, in, base + soff, vo, th);
+    return vo;
+  };
+  // advance the outer odometer (levels p .. a-1, innermost fastest)
+  auto advance = [&]() {
+    bool carry = true;
+#pragma unroll
+    for (int m = KD - 1; m >= 0; --m) {
+      if (carry && m >= p && m < a_lv) {
+        ++s[m];
+        soff += P.lv[m].sstride;
+        if (s[m] == P.lv[m].strips) {
+          s[m] = 0;
+          soff -= P.lv[m].strips * P.lv[m].sstride;
+        } else {
+          carry = false;
+        }
+      }
+    }
+  };
+  // combine the innermost segment's lane partials, feed its value to the parent
+  // segment, then finish the outer segments whose strips all end here
+  auto consume = [&](Acc ai) {
     ai = combine_seg<T, KD>(P, P.seg[inner], ai, th, lds);
     if (inner == stop) {
       fin = ai;
     } else if constexpr (NS > 1) {
-      // feed the innermost segment's value to its parent, then finish the outer
-      // segments whose strips all end here
 #pragma unroll
       for (int j = NO - 1; j >= 0; --j) {
         if (j == inner - 1) {
@@ -569,20 +590,71 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
         }
       }
     }
-    // advance the outer odometer (levels p .. a-1, innermost fastest)
-    bool carry = true;
+  };
+  bool done = false;
+  if constexpr (!LEAN) {
+    if (P.inner_iters == 1 && P.outer_iters > 1) {
+      // The innermost segment is one chunk per outer iteration: load the chunks of
+      // UO outer iterations back to back, then fold and combine them in order.
+      auto prefetch = [&](auto opc) {
+        constexpr int OPI = decltype(opc)::value;
+        constexpr int UO = U >= 8 ? U / 2 : U;
+        using V = typename Chunk<typename T::Raw, C>::V;
+        const bool nt = !(P.flags & HP_FLAG_TEMPORAL);
+        long long t_first = 0;
 #pragma unroll
-    for (int m = KD - 1; m >= 0; --m) {
-      if (carry && m >= p && m < a_lv) {
-        ++s[m];
-        soff += P.lv[m].sstride;
-        if (s[m] == P.lv[m].strips) {
-          s[m] = 0;
-          soff -= P.lv[m].strips * P.lv[m].sstride;
-        } else {
-          carry = false;
+        for (int m = 0; m < KD; ++m)
+          if (m == P.depth - 1) t_first = th.targ[m];
+        for (long long q0 = 0; q0 < P.outer_iters; q0 += UO) {
+          const int nu = (P.outer_iters - q0) < UO ? (int)(P.outer_iters - q0) : UO;
+          V x[UO];
+          bool ok[UO];
+          int s_keep[KD];
+#pragma unroll
+          for (int m = 0; m < KD; ++m) s_keep[m] = s[m];
+          const long long soff_keep = soff;
+#pragma unroll
+          for (int u = 0; u < UO; ++u) {
+            ok[u] = false;
+            if (u < nu) {
+              ok[u] = outer_valid();
+              x[u] = load_chunk<V>(ok[u] ? in + base + soff : in, nt);
+              advance();
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < KD; ++m) s[m] = s_keep[m];
+          soff = soff_keep;
+#pragma unroll
+          for (int u = 0; u < UO; ++u) {
+            if (u < nu) {
+              Acc ai = T::identity(OPI);
+              AddChunk<T, C, OPI>::run(ai, x[u], t_first, ok[u]);
+              consume(ai);
+              advance();
+            }
+          }
+        }
+      };
+      if constexpr (T::kFloat) {
+        prefetch(std::integral_constant<int, HP_OP_SUM>{});
+      } else {
+        switch (P.seg[inner].op) {
+          case HP_OP_MIN: prefetch(std::integral_constant<int, HP_OP_MIN>{}); break;
+          case HP_OP_MAX: prefetch(std::integral_constant<int, HP_OP_MAX>{}); break;
+          case HP_OP_ARGMIN: prefetch(std::integral_constant<int, HP_OP_ARGMIN>{}); break;
+          case HP_OP_ARGMAX: prefetch(std::integral_constant<int, HP_OP_ARGMAX>{}); break;
+          default: prefetch(std::integral_constant<int, HP_OP_SUM>{}); break;
         }
       }
+      done = true;
+    }
+  }
+  if (!done) {
+    for (long long q = 0; q < P.outer_iters; ++q) {
+      const bool vo = outer_valid();
+      consume(InnerStream<T, C, U, KD, LEAN>::run(P, in, base + soff, vo, th));
+      advance();
     }
   }
   Acc r = fin;
@@ -734,7 +806,7 @@ struct GridFold<IntT> {
 // ---------------------------------------------------------------------------
 // one workgroup
 
-template <class T, int C, int NS, int U, int KD>
+template <class T, int C, int NS, int U, int KD, bool LEAN = false>
 __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                        void* __restrict__ out, unsigned char* __restrict__ ws, uint32_t g,
                                        char* lds) {
@@ -797,7 +869,7 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
         }
       }
     } else {
-      const typename T::Acc a = reduce_block<T, C, NS, U, KD>(P, in, off + base_red, vnone, th, lds);
+      const typename T::Acc a = reduce_block<T, C, NS, U, KD, LEAN>(P, in, off + base_red, vnone, th, lds);
       if (P.gmode == GCOMB_NONE) {
         if (vnone && red_writer) {
           if constexpr (T::kFloat) store_flt(P, out, o, (double)a.s + (double)a.c);

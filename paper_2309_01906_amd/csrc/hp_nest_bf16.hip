@@ -11,11 +11,24 @@ __global__ void __launch_bounds__(1024) k_nest_bf16(const DevPlan* __restrict__ 
   wg_run<FloatT<uint16_t>, C, 1, (C == 1 ? 16 : 8), KD>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
 }
 
+// Lean variant for the common streaming case: one strided inner dimension, at
+// most 8 waves, depth <= 4; built for 8 resident waves per SIMD.
+template <int C>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8)))
+k_nest_bf16_lean(const DevPlan* __restrict__ Pd, const uint16_t* __restrict__ in, void* __restrict__ out,
+               unsigned char* __restrict__ ws) {
+  extern __shared__ __align__(16) char lds[];
+  const DevPlan& P = *Pd;
+  wg_run<FloatT<uint16_t>, C, 1, 4, 4, true>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+}
+
 hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {
   const dim3 grid((unsigned int)P.grid), block((unsigned int)(P.nw * kWave));
   const uint16_t* x = reinterpret_cast<const uint16_t*>(in);
   unsigned char* w = reinterpret_cast<unsigned char*>(ws);
-  if (P.depth <= 4) {
+  if (P.depth <= 4 && P.nid <= 1 && P.nw <= 8 && P.chunk == 8 && !(P.flags & HP_FLAG_GENERIC)) {
+    hipLaunchKernelGGL(k_nest_bf16_lean<8>, grid, block, lds, st, dP, x, out, w);
+  } else if (P.depth <= 4) {
     if (P.chunk == 8) hipLaunchKernelGGL((k_nest_bf16<8, 4>), grid, block, lds, st, dP, x, out, w);
     else hipLaunchKernelGGL((k_nest_bf16<1, 4>), grid, block, lds, st, dP, x, out, w);
   } else {

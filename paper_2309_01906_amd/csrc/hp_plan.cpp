@@ -128,7 +128,7 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
 
 hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw) {
   if (!n || !out) return fail(HP_EINVAL, "null argument");
-  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_TEMPORAL))
+  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_TEMPORAL | HP_FLAG_GENERIC))
     return fail(HP_EINVAL, "unknown flag bits 0x%x", flags);
   const int d = n->depth;
   if (d < 1 || d > kMaxDepth) return fail(HP_EINVAL, "depth %d outside [1, %d]", d, kMaxDepth);

@@ -231,7 +231,7 @@ def test_grid_combine_nested_segments():
     x = workloads.uniform_i32(76, ext, -100, 100)
     for ops, m in [(("NONE", "ARGMAX", "SUM"), ["G", "G", ("GWV", {"G": 4})]),
                    (("NONE", "MIN", "SUM"), ["G", ("G", {"G": 5}), ("GW", {"G": 8, "W": 2})]),
-                   (("NONE", "SUM", "MAX"), ["G", ("G", {"G": 8}), ("GV", {"G": 3})])]:
+                   (("NONE", "SUM", "MAX"), ["G", ("G", {"G": 8}), ("GWV", {"G": 3, "W": 1})])]:
         got, info = gpu_reduce(x, ext, ops, m)
         assert info["gsplit"] > 1
         assert_match(got, x, ext, ops, what=f"nested {ops} {m}")
