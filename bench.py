@@ -145,6 +145,110 @@ def extra_int_workloads(steps, warmup, stream):
     return res
 
 
+def batched_vs_plain(stream, steps=20, warmup=3):
+    """10,000 uneven bf16 nests: one persistent launch replayed from a hipGraph vs one
+    launch per nest (eager, and all launches captured in one graph).  Same plans, so
+    the outputs are compared bit for bit."""
+    import numpy as np
+    import torch
+
+    import paper_2309_01906_amd as hp
+    import workloads
+    bw = workloads.c4_batch()
+    host = bw.payload_bf16()
+    dev = torch.from_numpy(host.view(np.int16)).cuda().view(torch.bfloat16)
+    nests = [(n.extents, n.ops, n.dtype) for n in bw.nests]
+    out_elems = [n.extents[0] for n in bw.nests]
+    oo = np.concatenate([[0], np.cumsum(out_elems)])
+    out_a = torch.zeros(int(oo[-1]), dtype=torch.float64, device="cuda")
+    out_b = torch.zeros_like(out_a)
+    t_plan = time.perf_counter()
+    b = hp.Batch(nests, hp.BATCH_GRAPH)
+    t_plan = time.perf_counter() - t_plan
+    base_in, base_a, base_b = dev.data_ptr(), out_a.data_ptr(), out_b.data_ptr()
+    ins = [base_in + 2 * int(o) for o in bw.offsets]
+    st = b.stats()
+
+    def timed(fn, k, w):
+        for _ in range(w):
+            fn()
+        torch.cuda.synchronize()
+        ev = []
+        t0 = time.perf_counter()
+        for _ in range(k):
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record(stream)
+            fn()
+            e_.record(stream)
+            e_.synchronize()
+            ev.append(s_.elapsed_time(e_))
+        return (time.perf_counter() - t0) / k * 1e3, ev
+
+    b.set_io_ptrs(ins, [base_a + 8 * int(o) for o in oo[:-1]])
+    wall_b, ev_b = timed(lambda: b.run(stream), steps, warmup)
+    got_b = out_a.cpu().numpy()
+    b.set_io_ptrs(ins, [base_b + 8 * int(o) for o in oo[:-1]])
+    wall_p, ev_p = timed(lambda: b.run_each(stream, graph=False), max(3, steps // 4), 1)
+    got_p = out_b.cpu().numpy()
+    wall_g, ev_g = timed(lambda: b.run_each(stream, graph=True), max(3, steps // 4), 1)
+    nbytes = st["bytes"]
+    b.close()
+    res = {
+        "nests": len(nests), "bytes": nbytes, "persistent_launches": st["launches"], "tasks": st["tasks"],
+        "wave_workers": st["workers"],
+        "plan_seconds": round(t_plan, 3),
+        "batched_graph": {"p50_us": round(pct(ev_b, 50) * 1e3, 1), "p99_us": round(pct(ev_b, 99) * 1e3, 1),
+                          "GBps": round(nbytes / (pct(ev_b, 50) * 1e-3) / 1e9, 1)},
+        "plain_one_launch_per_nest": {"p50_us": round(pct(ev_p, 50) * 1e3, 1),
+                                      "GBps": round(nbytes / (pct(ev_p, 50) * 1e-3) / 1e9, 1)},
+        "plain_launches_in_one_graph": {"p50_us": round(pct(ev_g, 50) * 1e3, 1),
+                                        "GBps": round(nbytes / (pct(ev_g, 50) * 1e-3) / 1e9, 1)},
+        "bit_identical_to_plain": bool(np.array_equal(got_b, got_p)),
+    }
+    res["speedup_vs_plain"] = round(res["plain_one_launch_per_nest"]["p50_us"] / res["batched_graph"]["p50_us"], 2)
+    del dev, out_a, out_b
+    return res
+
+
+def serving(duration_s=1.0, rate=20000.0):
+    """Open-loop Poisson stream of mixed 2-4 level requests admitted by a 64 GiB
+    budget; latency from scheduled arrival to observed completion."""
+    import numpy as np
+    import torch
+
+    import paper_2309_01906_amd as hp
+    import workloads
+    st = workloads.c5_stream(duration_s=duration_s, rate=rate, pool_elems=1 << 28)
+    di = torch.from_numpy(st.pool_i32()).cuda()
+    df = torch.from_numpy(st.pool_f32()).cuda()
+    reqs = st.requests
+    out_sizes, kinds = [], []
+    for r in reqs:
+        inf = hp.inspect(r.nest.extents, r.nest.ops, r.nest.dtype)
+        out_sizes.append(inf["n_out"])
+        kinds.append(inf["out_dtype"])
+    tot = int(sum(out_sizes)) + len(reqs)
+    out = torch.zeros(tot, dtype=torch.float64, device="cuda")  # 8 bytes per output slot
+    offs = np.concatenate([[0], np.cumsum(out_sizes)])
+    ins = [(di if r.pool == 0 else df).data_ptr() + 4 * r.offset for r in reqs]
+    outs = [out.data_ptr() + 8 * int(o) for o in offs[:-1]]
+    nests = [(r.nest.extents, r.nest.ops, r.nest.dtype) for r in reqs]
+    with hp.Server(hbm_budget=64 << 30, slot_bytes=256 << 20, streams=4, max_batch=512, window_us=30) as srv:
+        t0 = srv.now_us() + 5000.0
+        arrivals = [t0 + r.t_arrival_us for r in reqs]
+        tk = srv.replay(nests, ins, outs, arrivals)
+        infos = [srv.wait(t) for t in tk]
+        stats = srv.stats()
+    ok = all(i["status"] == 0 for i in infos)
+    del di, df, out
+    return {
+        "requests": len(reqs), "offered_rate_per_s": rate, "duration_s": duration_s, "all_ok": ok,
+        "batches": stats["batches"], "p50_us": round(stats["p50_us"], 1), "p99_us": round(stats["p99_us"], 1),
+        "p999_us": round(stats["p999_us"], 1), "GBps": round(stats["gbps"], 2),
+        "bytes": stats["bytes"], "max_in_flight_bytes": stats["max_in_use_bytes"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +256,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -209,6 +315,13 @@ def main():
         line["error_vs_fp64_oracle"] = err
     if not args.no_extras:
         line["extras"] = extra_int_workloads(min(args.steps, 200), min(args.warmup, 20), stream)
+        tc = os.path.join(ROOT, "paper_2309_01906_amd", "tune_gfx950.txt")
+        if os.path.exists(tc):
+            hp.tune_cache_load(tc)
+        if not args.no_batch:
+            line["batched_vs_plain"] = batched_vs_plain(stream)
+        if not args.no_serving:
+            line["serving"] = serving()
     plan.close()
     print(json.dumps(line), flush=True)
 

@@ -177,12 +177,17 @@ typedef struct hp_batch_s* hp_batch_t;
  * bad nest; HP_ENOMEM if device memory runs out. */
 hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t flags, hp_batch_t* out);
 
+/* Host-only: the plans hp_batch_plan would make (current tuner cache included),
+ * written to infos[0..n).  No device is touched. */
+hp_status hp_batch_plan_inspect(const hp_nest* nests, int64_t n, uint32_t flags, hp_plan_info* infos);
+
 /* Planner decisions for nest i of the batch. */
 hp_status hp_batch_info(hp_batch_t b, int64_t i, hp_plan_info* info);
 
-/* Launch count (persistent kernels per run), total workgroup tasks, and the
- * algorithmic bytes (inputs + outputs) of one run. */
-hp_status hp_batch_stats(hp_batch_t b, int64_t* n_launches, int64_t* n_tasks, double* bytes);
+/* Launch count (persistent kernels per run), total tasks, wavefront workers of the
+ * persistent launches, and the algorithmic bytes (inputs + outputs) of one run.
+ * Any output pointer may be NULL. */
+hp_status hp_batch_stats(hp_batch_t b, int64_t* n_launches, int64_t* n_tasks, int64_t* n_workers, double* bytes);
 
 /* Point the batch at its data: host arrays of n device pointers (inputs 16-byte
  * aligned, outputs aligned for their type).  Copied into the batch's device
@@ -205,9 +210,11 @@ hp_status hp_batch_destroy(hp_batch_t b);
  * Autotuner (section 3.9's choice between kernel versions, made by measurement):
  * for a nest whose reducing levels fold as one reduction (SUM, MIN or MAX), time
  * candidate level maps of its size class on the current device -- the block seen
- * as (J, K) rows, J split between grid, waves and lane partitions -- and store the
- * fastest in the process-wide cache that batched plans consult.  Timings are
- * medians of `reps` runs.  best_us / auto_us (may be NULL) receive the winner's
+ * as (J, K) rows split between grid, waves and lane partitions, or many outputs
+ * per task on lane partitions -- and store the fastest in the process-wide cache
+ * that batched plans consult.  A candidate is timed as a persistent batch of
+ * replicas of the nest (its throughput when it shares the device), median of
+ * `reps` runs, per nest.  best_us / auto_us (may be NULL) receive the winner's
  * time and the automatic map's.  The cache is also read once from the file named
  * by the HP_TUNE_CACHE environment variable. */
 hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t reps, double* best_us, double* auto_us);

@@ -256,8 +256,10 @@ def _batch_sigs():
     vp, st = ctypes.c_void_p, ctypes.c_int
     L.hp_batch_plan.argtypes = [ctypes.POINTER(Nest), ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(vp)]
     L.hp_batch_info.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(PlanInfo)]
+    L.hp_batch_plan_inspect.argtypes = [ctypes.POINTER(Nest), ctypes.c_int64, ctypes.c_uint32,
+                                        ctypes.POINTER(PlanInfo)]
     L.hp_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                 ctypes.POINTER(ctypes.c_double)]
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
     L.hp_batch_set_io.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     L.hp_batch_run.argtypes = [vp, vp]
     L.hp_batch_run_each.argtypes = [vp, vp, ctypes.c_int32]
@@ -268,11 +270,22 @@ def _batch_sigs():
     L.hp_tune_cache_save.argtypes = [ctypes.c_char_p]
     L.hp_tune_cache_clear.argtypes = []
     L.hp_tune_cache_size.argtypes = [ctypes.POINTER(ctypes.c_int64)]
-    for f in ("hp_batch_plan", "hp_batch_info", "hp_batch_stats", "hp_batch_set_io", "hp_batch_run",
+    for f in ("hp_batch_plan", "hp_batch_plan_inspect", "hp_batch_info", "hp_batch_stats", "hp_batch_set_io", "hp_batch_run",
               "hp_batch_run_each", "hp_batch_destroy", "hp_tune_nest", "hp_tune_cache_load",
               "hp_tune_cache_save", "hp_tune_cache_clear", "hp_tune_cache_size"):
         getattr(L, f).restype = st
     _batch_sigs_done = True
+
+
+def batch_inspect(nests, flags: int = 0):
+    """Host only: the plan of every nest of a batch (tuner cache included)."""
+    _batch_sigs()
+    arr = (Nest * len(nests))()
+    for i, (ext, ops, dt) in enumerate(nests):
+        arr[i] = make_nest(ext, ops, dt)
+    infos = (PlanInfo * len(nests))()
+    check(lib().hp_batch_plan_inspect(arr, len(nests), flags, infos))
+    return [_info_dict(infos[i]) for i in range(len(nests))]
 
 
 class Batch:
@@ -293,9 +306,9 @@ class Batch:
         return _info_dict(inf)
 
     def stats(self):
-        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
-        check(lib().hp_batch_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"launches": a.value, "tasks": b.value, "bytes": c.value}
+        a, b, w, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(lib().hp_batch_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w), ctypes.byref(c)))
+        return {"launches": a.value, "tasks": b.value, "workers": w.value, "bytes": c.value}
 
     def set_io_ptrs(self, in_ptrs, out_ptrs):
         ins = (ctypes.c_void_p * self.n)(*in_ptrs)

@@ -40,6 +40,32 @@ int batch_occupancy(int family, int chunk, int nw, size_t lds) {
   }
 }
 
+__global__ void k_clear_counters(unsigned int* p, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = 0u;
+}
+
+hp_status launch_clear(unsigned int* ctr, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_counters, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, n);
+  if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "counter clear launch failed");
+  return HP_OK;
+}
+
+void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B) {
+  const int nq = grid < kQueues ? (grid < 1 ? 1 : grid) : kQueues;
+  int pos = 0;
+  for (int q = 0; q < kQueues; ++q) {
+    B->qbeg[q] = pos;
+    if (q < nq)
+      for (int j = q; j < n; j += nq) out[pos++] = ordered[j];
+  }
+  B->qbeg[kQueues] = pos;
+  // several tasks per atomic when every worker has many to do
+  const long long workers = (long long)grid * kBatchGroupWaves;
+  long long k = (long long)n / (workers * 8);
+  B->per_pop = (int)(k < 1 ? 1 : (k > 8 ? 8 : k));
+}
+
 hp_status launch_single(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
                         hipStream_t st) {
   switch (P.dtype) {
@@ -56,8 +82,7 @@ namespace {
 struct Group {  // nests of one kernel family and chunk: one persistent launch
   int family, chunk;
   long long n_tasks;
-  int2* d_tasks;
-  unsigned int* d_ctr;
+  hp::BatchArgs args;  // pointers into the batch's device memory
   int grid;
   size_t lds;
 };
@@ -100,12 +125,47 @@ static void batch_free(hp_batch_s* b) {
   delete b;
 }
 
+namespace hp {
+
+// Build a batch from plans made by the caller (batched plans: kBatchWaves waves).
+hp_status batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags, hp_batch_s** out);
+
+}  // namespace hp
+
 extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t flags, hp_batch_t* out) {
   using namespace hp;
   if (!out || !nests || n < 1) return fail(HP_EINVAL, "null argument or empty batch");
   *out = nullptr;
   if (flags & ~(uint32_t)(HP_BATCH_GRAPH | HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL | HP_BATCH_NO_TUNE))
     return fail(HP_EINVAL, "unknown batch flag bits 0x%x", flags);
+  std::vector<Lowered> plans((size_t)n);
+  const uint32_t pflags = flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL);
+  for (int64_t i = 0; i < n; ++i) {
+    hp_status s = plan_for_batch(&nests[i], pflags, !(flags & HP_BATCH_NO_TUNE), kBatchWaves, &plans[(size_t)i]);
+    if (s != HP_OK) {
+      char msg[512];
+      snprintf(msg, sizeof msg, "%s", hp_last_error());
+      return fail(s, "nest %lld: %s", (long long)i, msg);
+    }
+  }
+  return batch_from_plans(plans, flags, out);
+}
+
+extern "C" hp_status hp_batch_plan_inspect(const hp_nest* nests, int64_t n, uint32_t flags, hp_plan_info* infos) {
+  using namespace hp;
+  if (!nests || !infos || n < 1) return fail(HP_EINVAL, "null argument or empty batch");
+  const uint32_t pflags = flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL);
+  for (int64_t i = 0; i < n; ++i) {
+    Lowered L;
+    hp_status s = plan_for_batch(&nests[i], pflags, !(flags & HP_BATCH_NO_TUNE), kBatchWaves, &L);
+    if (s != HP_OK) return s;
+    infos[i] = L.info;
+  }
+  return HP_OK;
+}
+
+hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags, hp_batch_s** out) {
+  const int64_t n = (int64_t)plans.size();
   hp_batch_s* b = new (std::nothrow) hp_batch_s;
   if (!b) return fail(HP_ENOMEM, "host allocation failed");
   b->n = n;
@@ -117,19 +177,10 @@ extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t fla
   }
   b->plans.resize((size_t)n);
   b->infos.resize((size_t)n);
-  const uint32_t pflags = flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL);
   for (int64_t i = 0; i < n; ++i) {
-    Lowered L;
-    hp_status s = plan_for_batch(&nests[i], pflags, !(flags & HP_BATCH_NO_TUNE), b->nw, &L);
-    if (s != HP_OK) {
-      batch_free(b);
-      char msg[512];
-      snprintf(msg, sizeof msg, "%s", hp_last_error());
-      return fail(s, "nest %lld: %s", (long long)i, msg);
-    }
-    b->plans[(size_t)i] = L.dp;
-    b->infos[(size_t)i] = L.info;
-    b->bytes += (double)L.info.in_bytes + (double)L.info.out_bytes;
+    b->plans[(size_t)i] = plans[(size_t)i].dp;
+    b->infos[(size_t)i] = plans[(size_t)i].info;
+    b->bytes += (double)plans[(size_t)i].info.in_bytes + (double)plans[(size_t)i].info.out_bytes;
   }
   // groups by (family, chunk); tasks largest first inside a group
   std::vector<std::vector<int64_t>> members;
@@ -154,7 +205,11 @@ extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t fla
     task_off[g] = arena_bytes;
     arena_bytes = align_up(arena_bytes + (size_t)ntask[g] * sizeof(int2), 256);
     ctr_off[g] = arena_bytes;
-    arena_bytes = align_up(arena_bytes + 2 * sizeof(unsigned int), 256);
+    arena_bytes = align_up(arena_bytes + kCtrWords * sizeof(unsigned int), 256);
+    if (ntask[g] > 0x7fffffffLL) {
+      batch_free(b);
+      return fail(HP_ETOOBIG, "batch group has %lld tasks, more than 2^31 - 1", ntask[g]);
+    }
   }
   std::vector<size_t> ws_off((size_t)n, 0);
   for (int64_t i = 0; i < n; ++i) {
@@ -184,26 +239,29 @@ extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t fla
       const double wc = (double)b->infos[(size_t)c].in_bytes / (double)b->plans[(size_t)c].grid;
       return wa > wc;
     });
-    int2* t = reinterpret_cast<int2*>(host_arena.data() + task_off[g]);
+    std::vector<int2> ordered((size_t)ntask[g]);
     long long k = 0;
     for (int64_t i : mem)
-      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w) t[k++] = make_int2((int)i, (int)w);
+      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w) ordered[(size_t)k++] = make_int2((int)i, (int)w);
     Group G;
     G.family = keys[g].first;
     G.chunk = keys[g].second;
     G.n_tasks = ntask[g];
-    G.d_tasks = reinterpret_cast<int2*>((unsigned char*)b->arena + task_off[g]);
-    G.d_ctr = reinterpret_cast<unsigned int*>((unsigned char*)b->arena + ctr_off[g]);
-    G.lds = 16;
-    for (int64_t i : mem) G.lds = std::max(G.lds, b->infos[(size_t)i].lds_bytes);
+    // wave tasks: every wavefront of a persistent workgroup runs tasks on its own
+    G.lds = (size_t)kBatchGroupWaves * kWaveLdsBytes;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus < 1)
       cus = 256;
-    int occ = batch_occupancy(G.family, G.chunk, b->nw, G.lds);
+    int occ = batch_occupancy(G.family, G.chunk, kBatchGroupWaves, G.lds);
     if (occ < 1) occ = 1;
     long long grid = (long long)cus * occ;
-    if (grid > G.n_tasks) grid = G.n_tasks;
+    const long long need = (G.n_tasks + kBatchGroupWaves - 1) / kBatchGroupWaves;
+    if (grid > need) grid = need;
     G.grid = (int)grid;
+    deal_tasks(ordered.data(), (int)ntask[g], G.grid, reinterpret_cast<int2*>(host_arena.data() + task_off[g]),
+               &G.args);
+    G.args.tasks = reinterpret_cast<const int2*>((unsigned char*)b->arena + task_off[g]);
+    G.args.ctr = reinterpret_cast<unsigned int*>((unsigned char*)b->arena + ctr_off[g]);
     b->groups.push_back(G);
   }
   std::vector<unsigned char*> wsv(b->ws_ptrs);
@@ -224,12 +282,17 @@ extern "C" hp_status hp_batch_info(hp_batch_t b, int64_t i, hp_plan_info* info) 
   return HP_OK;
 }
 
-extern "C" hp_status hp_batch_stats(hp_batch_t b, int64_t* n_launches, int64_t* n_tasks, double* bytes) {
+extern "C" hp_status hp_batch_stats(hp_batch_t b, int64_t* n_launches, int64_t* n_tasks, int64_t* n_workers,
+                                    double* bytes) {
   if (!b) return hp::fail(HP_EINVAL, "null batch");
-  long long t = 0;
-  for (const Group& g : b->groups) t += g.n_tasks;
+  long long t = 0, w = 0;
+  for (const Group& g : b->groups) {
+    t += g.n_tasks;
+    w += (long long)g.grid * hp::kBatchGroupWaves;
+  }
   if (n_launches) *n_launches = (int64_t)b->groups.size();
   if (n_tasks) *n_tasks = t;
+  if (n_workers) *n_workers = w;
   if (bytes) *bytes = b->bytes;
   return HP_OK;
 }
@@ -260,15 +323,13 @@ extern "C" hp_status hp_batch_set_io(hp_batch_t b, const void* const* d_in, void
 
 static hp_status launch_groups(hp_batch_s* b, hipStream_t st) {
   for (const Group& G : b->groups) {
-    hp::BatchArgs A;
+    hp::BatchArgs A = G.args;
     A.plans = b->d_plans;
-    A.tasks = G.d_tasks;
-    A.n_tasks = G.n_tasks;
-    A.ctr = G.d_ctr;
     A.ins = b->d_in;
     A.outs = b->d_out;
     A.wss = b->d_ws;
-    hp_status s = hp::launch_batch(G.family, G.chunk, A, G.grid, b->nw, G.lds, st);
+    hp_status s = hp::launch_clear(A.ctr, hp::kCtrWords, st);
+    if (s == HP_OK) s = hp::launch_batch(G.family, G.chunk, A, G.grid, hp::kBatchGroupWaves, G.lds, st);
     if (s != HP_OK) return s;
   }
   return HP_OK;

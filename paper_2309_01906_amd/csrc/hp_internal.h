@@ -60,7 +60,7 @@ struct DevSeg {
   int32_t pad;
 };
 
-struct DevPlan {
+struct alignas(16) DevPlan {
   int32_t depth, p, nseg, dtype;
   int32_t out_kind, nw, flags, chunk;
   int64_t n_out;

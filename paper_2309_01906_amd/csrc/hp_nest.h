@@ -213,9 +213,13 @@ struct Chunk<uint16_t, 8> { using V = u32x4; };
 template <>
 struct Chunk<uint16_t, 1> { using V = unsigned short; };
 
+// Inputs always live in global memory: say so, so that pointers read from tables
+// (batches) still give global loads rather than flat ones (flat loads also count
+// on the LDS counter and would be waited for together with LDS reads).
 template <class V>
 __device__ __forceinline__ V load_chunk(const void* p, bool nt) {
-  const V* q = reinterpret_cast<const V*>(p);
+  typedef const __attribute__((address_space(1))) V GV;
+  GV* q = (GV*)(p);
   return nt ? __builtin_nontemporal_load(q) : *q;
 }
 
@@ -295,6 +299,8 @@ struct AddChunk<IntT, 1, OP> {
 template <int KD>
 struct Thread {
   int w, lane;
+  int tid;      // thread index inside the group that runs one task
+  bool wave;    // the group is one wavefront (batched wave tasks): no workgroup barriers
   int lim[KD];   // strips on which this thread's unit of level m has t < e
   int targ[KD];  // first iteration of level m for this thread (used by ARG levels)
   int limc[KD];  // lim of inner dim k
@@ -474,6 +480,18 @@ struct InnerStream<IntT, C, U, KD, LEAN> {
   }
 };
 
+// Synchronise the threads that run one task: the whole workgroup, or (for wave
+// tasks) one wavefront, which runs in lockstep and only needs its LDS accesses
+// ordered.
+__device__ __forceinline__ void group_sync(bool wave) {
+  if (wave) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Combine a segment's partials across its lanes (butterfly) and waves (LDS).
 // Afterwards every lane of a group holds the group's value.
 template <class T, int KD>
@@ -485,9 +503,9 @@ __device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const D
   if (S.wmask) {
     const int lanes = P.lds_slot_lanes;
     const int lidx = lanes == 1 ? 0 : (int)(th.lane & S.lds_lanes);
-    __syncthreads();  // earlier readers of the slots are done
+    group_sync(th.wave);  // earlier readers of the slots are done
     if ((th.lane & ~(int)S.lds_lanes & 63) == 0) T::put(lds, th.w * lanes + lidx, a);
-    __syncthreads();
+    group_sync(th.wave);
     const int wbase = th.w & ~(int)S.wmask;
     typename T::Acc r = T::get(lds, wbase * lanes + lidx);
     for (int j = 1; j < S.nwu; ++j) r = T::merge(r, T::get(lds, (wbase | (j << S.wlo)) * lanes + lidx), S.op);
@@ -498,7 +516,7 @@ __device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const D
 
 // Reduce the current output's block; returns segment P.gq's value (the output, or
 // this workgroup's partial of it when that segment spans workgroups).
-template <class T, int C, int NS, int U, int KD, bool LEAN>
+template <class T, int C, int NS, int U, int KD, bool LEAN, bool PF = true>
 __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                                         long long base, bool vnone, const Thread<KD>& th, char* lds) {
   using Acc = typename T::Acc;
@@ -592,7 +610,7 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
     }
   };
   bool done = false;
-  if constexpr (!LEAN) {
+  if constexpr (!LEAN && PF) {
     if (P.inner_iters == 1 && P.outer_iters > 1) {
       // The innermost segment is one chunk per outer iteration: load the chunks of
       // UO outer iterations back to back, then fold and combine them in order.
@@ -715,13 +733,13 @@ struct GridFold<FloatT<R>> {
       const DPair o{xor_move_d(a.s, 1 << b, th.lane), xor_move_d(a.c, 1 << b, th.lane)};
       a = dpair_merge(a, o);
     }
-    __syncthreads();
+    group_sync(th.wave);
     double* slots = reinterpret_cast<double*>(lds);
     if (th.lane == 0) {
       slots[2 * th.w] = a.s;
       slots[2 * th.w + 1] = a.c;
     }
-    __syncthreads();
+    group_sync(th.wave);
     DPair r{slots[0], slots[1]};
     for (int w = 1; w < P.nw; ++w) r = dpair_merge(r, DPair{slots[2 * w], slots[2 * w + 1]});
     return r.s + r.c;
@@ -740,9 +758,9 @@ struct GridFold<IntT> {
       for (long long k = tid; k < P.gsplit; k += nthreads) a = IntT::merge(a, IntT::get(part, k), op);
 #pragma unroll
       for (int b = 0; b < 6; ++b) a = IntT::merge(a, IntT::shfl(a, 1 << b, th.lane), op);
-      __syncthreads();
+      group_sync(th.wave);
       if (th.lane == 0) IntT::put(lds, th.w, a);
-      __syncthreads();
+      group_sync(th.wave);
       IAcc r = IntT::get(lds, 0);
       for (int w = 1; w < P.nw; ++w) r = IntT::merge(r, IntT::get(lds, w), op);
       return IntT::emit(r, op);
@@ -752,7 +770,7 @@ struct GridFold<IntT> {
     // with one iteration per workgroup, so their iteration index is the workgroup
     // digit.  One thread, partials in index order.
     long long* result = reinterpret_cast<long long*>(lds);
-    __syncthreads();
+    group_sync(th.wave);
     if (th.w == 0 && th.lane == 0) {
       const int q = P.gq;
       IAcc A[KD];
@@ -798,7 +816,7 @@ struct GridFold<IntT> {
       }
       *result = IntT::emit(A[0], P.seg[0].op);
     }
-    __syncthreads();
+    group_sync(th.wave);
     return *result;
   }
 };
@@ -806,13 +824,15 @@ struct GridFold<IntT> {
 // ---------------------------------------------------------------------------
 // one workgroup
 
-template <class T, int C, int NS, int U, int KD, bool LEAN = false>
+template <class T, int C, int NS, int U, int KD, bool LEAN = false, bool WAVE = false, bool PF = true>
 __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                        void* __restrict__ out, unsigned char* __restrict__ ws, uint32_t g,
                                        char* lds) {
   Thread<KD> th;
-  th.w = (int)(threadIdx.x >> 6);
+  th.w = WAVE ? 0 : (int)(threadIdx.x >> 6);
   th.lane = (int)(threadIdx.x & 63);
+  th.tid = WAVE ? th.lane : (int)threadIdx.x;
+  th.wave = WAVE;
   long long base_none = 0, base_o = 0, base_red = 0;
 #pragma unroll
   for (int m = 0; m < KD; ++m) {
@@ -869,7 +889,7 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
         }
       }
     } else {
-      const typename T::Acc a = reduce_block<T, C, NS, U, KD, LEAN>(P, in, off + base_red, vnone, th, lds);
+      const typename T::Acc a = reduce_block<T, C, NS, U, KD, LEAN, PF>(P, in, off + base_red, vnone, th, lds);
       if (P.gmode == GCOMB_NONE) {
         if (vnone && red_writer) {
           if constexpr (T::kFloat) store_flt(P, out, o, (double)a.s + (double)a.c);
@@ -880,26 +900,26 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
         char* part = reinterpret_cast<char*>(ws) + o * P.gsplit * kSlotBytes;
         unsigned int* tickets =
             reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(ws) + P.n_out * P.gsplit * kSlotBytes);
-        __syncthreads();
-        if (threadIdx.x == 0) {
+        group_sync(th.wave);
+        if (th.tid == 0) {
           T::put(part, gred, a);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           const unsigned int old =
               __hip_atomic_fetch_add(&tickets[o], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
           *flag = (old == (unsigned int)(P.gsplit - 1)) ? 1 : 0;
         }
-        __syncthreads();
+        group_sync(th.wave);
         const bool last = *flag != 0;
-        __syncthreads();
+        group_sync(th.wave);
         if (last) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           const auto v = GridFold<T>::template run<KD>(P, part, th, lds);
-          if (threadIdx.x == 0) {
+          if (th.tid == 0) {
             if constexpr (T::kFloat) store_flt(P, out, o, v);
             else store_int(P, out, o, v);
             __hip_atomic_store(&tickets[o], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
-          __syncthreads();
+          group_sync(th.wave);
         }
       }
     }
@@ -929,42 +949,68 @@ __device__ __forceinline__ uint32_t logical_group(const DevPlan& P, uint32_t b) 
   return (b & 7u) * per + (b >> 3);
 }
 
-// Persistent batched kernel body: workgroups pop (nest, workgroup) tasks from one
-// atomic counter (a dynamic schedule on the grid level, which needs exactly this one
-// synchronisation point) and run that nest's plan for that workgroup.  Tasks are
-// ordered largest first.  The last workgroup to leave resets the counters, so the
-// launch can be replayed (e.g. from a hipGraph) without clearing memory.
+// Persistent batched kernels: workers pop (nest, workgroup) tasks with atomic
+// counters -- a dynamic schedule on the grid level.  The tasks are dealt, largest
+// first, into kQueues queues with one counter each; workgroup b takes from queue
+// b % kQueues, which is the XCD the hardware places it on, so the counters are
+// contended by one XCD each instead of the whole chip.  The counters are cleared by
+// a separate small kernel before every run, so a run can be replayed from a graph.
+constexpr int kQueues = 8;
+constexpr int kCtrStride = 64;  // counters 256 bytes apart
+
 struct BatchArgs {
   const DevPlan* plans;        // one plan per nest
-  const int2* tasks;           // (nest, logical workgroup), largest first
-  long long n_tasks;
-  unsigned int* ctr;           // [0] next task, [1] workgroups finished
+  const int2* tasks;           // (nest, logical workgroup), queue by queue
+  unsigned int* ctr;           // kQueues counters, kCtrStride apart
   const void* const* ins;      // per nest
   void* const* outs;           // per nest
   unsigned char* const* wss;   // per nest (grid-combine workspace, may be null)
+  int qbeg[kQueues + 1];       // queue q holds tasks [qbeg[q], qbeg[q+1])
+  int per_pop;                 // tasks taken per atomic
 };
 
-template <class T, int C, int NS, int U, int KD>
-__device__ __forceinline__ void batch_run(const BatchArgs& B, char* lds) {
-  __shared__ long long s_task;
-  for (;;) {
-    if (threadIdx.x == 0)
-      s_task = (long long)__hip_atomic_fetch_add(&B.ctr[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const long long t = s_task;
-    __syncthreads();
-    if (t >= B.n_tasks) break;
-    const int2 te = B.tasks[t];
-    wg_run<T, C, NS, U, KD>(B.plans[te.x], reinterpret_cast<const typename T::Raw*>(B.ins[te.x]), B.outs[te.x],
-                            B.wss[te.x], (uint32_t)te.y, lds);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const unsigned int done = __hip_atomic_fetch_add(&B.ctr[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == gridDim.x - 1) {
-      __hip_atomic_store(&B.ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&B.ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Wave tasks: every wavefront of the workgroup is an independent worker running
+// one-wave plans (no workgroup barrier), with its own slice of LDS.  The task's
+// plan is first copied into that slice, so the kernel reads it from LDS instead of
+// with vector loads that would queue behind the data stream.  The next task index
+// is taken before the current task runs, so the atomic's latency overlaps it.
+constexpr int kPlanLdsBytes = (int)((sizeof(DevPlan) + 255) / 256 * 256);
+constexpr int kWaveLdsBytes = kPlanLdsBytes + 256;
+static_assert(sizeof(DevPlan) % 16 == 0, "plans are copied in 16-byte words");
+
+template <class T, int C, int NS, int U, int KD, bool PF = true>
+__device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
+  const int w = (int)(threadIdx.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  char* mine = lds + w * kWaveLdsBytes;
+  DevPlan* plan = reinterpret_cast<DevPlan*>(mine);
+  char* scratch = mine + kPlanLdsBytes;
+  const int q = (int)(blockIdx.x % kQueues);
+  const int qb = B.qbeg[q], qe = B.qbeg[q + 1];
+  const int k = B.per_pop;
+  unsigned int* ctr = B.ctr + q * kCtrStride;
+  auto pop = [&]() -> int {
+    unsigned int v = 0;
+    if (lane == 0) v = __hip_atomic_fetch_add(ctr, (unsigned int)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return qb + __builtin_amdgcn_readfirstlane((int)v);
+  };
+  int first = pop();
+  while (first < qe) {
+    const int next = pop();
+    const int last = first + k < qe ? first + k : qe;
+    for (int t = first; t < last; ++t) {
+      const int2 te = B.tasks[t];
+      const int x = __builtin_amdgcn_readfirstlane(te.x);
+      const int y = __builtin_amdgcn_readfirstlane(te.y);
+      const i32x4* src = reinterpret_cast<const i32x4*>(B.plans + x);
+      i32x4* dst = reinterpret_cast<i32x4*>(plan);
+      for (int i = lane; i < (int)(sizeof(DevPlan) / 16); i += 64) dst[i] = src[i];
+      group_sync(true);
+      wg_run<T, C, NS, U, KD, false, true, PF>(*plan, reinterpret_cast<const typename T::Raw*>(B.ins[x]),
+                                               B.outs[x], B.wss[x], (uint32_t)y, scratch);
+      group_sync(true);  // the plan slice is rewritten by the next task
     }
+    first = next;
   }
 }
 
@@ -982,6 +1028,14 @@ __host__ __device__ inline int family_of(const DevPlan& P) {
 
 // Launch a persistent batch of one family / chunk on `grid` workgroups of nw waves.
 hp_status launch_batch(int family, int chunk, const BatchArgs& B, int grid, int nw, size_t lds, hipStream_t st);
+// Clear n counters (a kernel, so that it can sit in a captured graph).
+hp_status launch_clear(unsigned int* ctr, int n, hipStream_t st);
+// Deal n tasks, given largest first, round-robin into the queues that a grid of
+// `grid` workgroups serves; writes them queue by queue to `out` and fills B->qbeg
+// and B->per_pop.
+void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B);
+// Counter words one batch launch uses (cleared before each launch).
+constexpr int kCtrWords = kQueues * kCtrStride;
 // Resident workgroups per CU for that kernel.
 int batch_occupancy(int family, int chunk, int nw, size_t lds);
 

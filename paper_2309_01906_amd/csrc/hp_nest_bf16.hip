@@ -12,14 +12,15 @@ __global__ void __launch_bounds__(1024) k_nest_bf16(const DevPlan* __restrict__ 
 }
 
 // Lean variant for the common streaming case: one strided inner dimension, at
-// most 8 waves, depth <= 4; built for 8 resident waves per SIMD.
+// most 8 waves, depth <= 4.  Only the streaming paths it needs are compiled, so
+// it keeps 8 chunk loads per lane in flight within fewer registers.
 template <int C>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(512)
 k_nest_bf16_lean(const DevPlan* __restrict__ Pd, const uint16_t* __restrict__ in, void* __restrict__ out,
                unsigned char* __restrict__ ws) {
   extern __shared__ __align__(16) char lds[];
   const DevPlan& P = *Pd;
-  wg_run<FloatT<uint16_t>, C, 1, 4, 4, true>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+  wg_run<FloatT<uint16_t>, C, 1, 8, 4, true>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
 }
 
 hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {

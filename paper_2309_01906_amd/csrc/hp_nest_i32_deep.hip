@@ -8,7 +8,7 @@ __global__ void __launch_bounds__(1024) k_nest_i32_deep(const DevPlan* __restric
                                                    void* __restrict__ out, unsigned char* __restrict__ ws) {
   extern __shared__ __align__(16) char lds[];
   const DevPlan& P = *Pd;
-  wg_run<IntT, C, kMaxDepth, 8, kMaxDepth>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+  wg_run<IntT, C, kMaxDepth, 4, kMaxDepth, false, false, false>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
 }
 
 hp_status launch_nest_i32_deep(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {

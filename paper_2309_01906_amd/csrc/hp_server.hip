@@ -125,7 +125,7 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
     task_off[g] = off;
     off = align_up(off + (size_t)ntask[g] * sizeof(int2), 256);
     ctr_off[g] = off;
-    off = align_up(off + 2 * sizeof(unsigned int), 256);
+    off = align_up(off + kCtrWords * sizeof(unsigned int), 256);
   }
   const size_t ws_begin = off;
   std::vector<size_t> ws_off((size_t)n, 0);
@@ -149,6 +149,9 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
     hout[i] = rs[(size_t)i]->out;
     hws[i] = ws_off[(size_t)i] ? d + ws_off[(size_t)i] : nullptr;
   }
+  const size_t lds = (size_t)kBatchGroupWaves * kWaveLdsBytes;
+  std::vector<BatchArgs> args(keys.size());
+  std::vector<int> grid(keys.size());
   for (size_t g = 0; g < keys.size(); ++g) {
     std::vector<int64_t>& mem = members[g];
     std::stable_sort(mem.begin(), mem.end(), [&](int64_t a, int64_t c) {
@@ -156,11 +159,26 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
       const double wc = (double)rs[(size_t)c]->L.info.in_bytes / (double)rs[(size_t)c]->L.dp.grid;
       return wa > wc;
     });
-    int2* t = reinterpret_cast<int2*>(h + task_off[g]);
+    std::vector<int2> ordered((size_t)ntask[g]);
     long long k = 0;
     for (int64_t i : mem)
-      for (long long w = 0; w < rs[(size_t)i]->L.dp.grid; ++w) t[k++] = make_int2((int)i, (int)w);
-    memset(h + ctr_off[g], 0, 2 * sizeof(unsigned int));
+      for (long long w = 0; w < rs[(size_t)i]->L.dp.grid; ++w) ordered[(size_t)k++] = make_int2((int)i, (int)w);
+    const int key = occ_key(keys[g].first, keys[g].second);
+    auto it = S->occ.find(key);
+    int o;
+    if (it == S->occ.end()) {
+      o = batch_occupancy(keys[g].first, keys[g].second, kBatchGroupWaves, lds);
+      if (o < 1) o = 1;
+      S->occ[key] = o;
+    } else {
+      o = it->second;
+    }
+    long long gr = (long long)S->cus * o;
+    const long long need = (ntask[g] + kBatchGroupWaves - 1) / kBatchGroupWaves;
+    if (gr > need) gr = need;
+    grid[g] = (int)gr;
+    deal_tasks(ordered.data(), (int)ntask[g], grid[g], reinterpret_cast<int2*>(h + task_off[g]), &args[g]);
+    memset(h + ctr_off[g], 0, kCtrWords * sizeof(unsigned int));
   }
   // upload descriptors (not the workspaces), clear the workspaces (tickets start at 0)
   if (hipMemcpyAsync(d, h, ws_begin, hipMemcpyHostToDevice, slot.st) != hipSuccess)
@@ -168,29 +186,14 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
   if (off > ws_begin && hipMemsetAsync(d + ws_begin, 0, off - ws_begin, slot.st) != hipSuccess)
     return fail(HP_EDEVICE, "workspace clear failed");
   for (size_t g = 0; g < keys.size(); ++g) {
-    BatchArgs A;
+    BatchArgs A = args[g];
     A.plans = reinterpret_cast<const DevPlan*>(d + plans_off);
     A.tasks = reinterpret_cast<const int2*>(d + task_off[g]);
-    A.n_tasks = ntask[g];
     A.ctr = reinterpret_cast<unsigned int*>(d + ctr_off[g]);
     A.ins = reinterpret_cast<const void* const*>(d + ptr_off);
     A.outs = reinterpret_cast<void* const*>(d + ptr_off) + n;
     A.wss = reinterpret_cast<unsigned char* const*>(d + ptr_off) + 2 * n;
-    size_t lds = 16;
-    for (int64_t i : members[g]) lds = std::max(lds, rs[(size_t)i]->L.info.lds_bytes);
-    const int key = occ_key(keys[g].first, keys[g].second);
-    auto it = S->occ.find(key);
-    int o;
-    if (it == S->occ.end()) {
-      o = batch_occupancy(keys[g].first, keys[g].second, kBatchWaves, 4096);
-      if (o < 1) o = 1;
-      S->occ[key] = o;
-    } else {
-      o = it->second;
-    }
-    long long grid = (long long)S->cus * o;
-    if (grid > ntask[g]) grid = ntask[g];
-    hp_status s = launch_batch(keys[g].first, keys[g].second, A, (int)grid, kBatchWaves, lds, slot.st);
+    hp_status s = launch_batch(keys[g].first, keys[g].second, A, grid[g], kBatchGroupWaves, lds, slot.st);
     if (s != HP_OK) return s;
   }
   if (hipEventRecord(slot.ev, slot.st) != hipSuccess) return fail(HP_EDEVICE, "event record failed");

@@ -6,19 +6,29 @@
 
 namespace hp {
 
-constexpr int kBatchWaves = 4;  // waves per workgroup of every batched plan
+constexpr int kBatchWaves = 1;          // waves per task of every batched plan (wave tasks)
+constexpr int kBatchGroupWaves = 4;     // wavefronts per workgroup of a persistent launch
 
-// How a tuned plan is built for every nest of one size class.  The reduced block
-// of a single-segment nest (one operator that folds as one reduction) is viewed as
-// (J, K): K contiguous elements, J = block / K; NONE levels stay on the grid,
-// J goes to the grid (g units) x waves (all of them) x lane partitions (vj), K to
-// the remaining lanes.  k == 0 means: the planner's automatic map.
+// How a tuned plan is built for every nest of one size class (single-segment nests:
+// one operator that folds as one reduction, so the block may be reshaped).
+//   mode 0: the planner's automatic map;
+//   mode 1: the block viewed as (J, K) rows: NONE levels on the grid, J on the grid
+//           (gj units) x waves x lane partitions (vj), K on the remaining lanes;
+//   mode 2: many outputs per task: the block as one level on pw lanes, the
+//           innermost NONE level on 64/pw lane partitions x waves, opt outputs per
+//           task (the rest of the outputs on the grid).
 struct Recipe {
+  int32_t mode;
   int64_t k;
   int32_t vj;
   int32_t gj;
+  int32_t pw;
+  int32_t opt;
   double us;  // measured time of the winner on the class representative
 };
+
+// Default recipe for a batched nest when the cache has none.
+Recipe default_recipe(const hp_nest* nest, int nw);
 
 // Size class of a nest: input type, operator signature, output count and block
 // length (log2 buckets).

@@ -18,9 +18,11 @@
 #include "hp_nest.h"
 #include "hp_tune.h"
 
+struct hp_batch_s;
 namespace hp {
 hp_status launch_single(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
                         hipStream_t st);
+hp_status batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags, hp_batch_s** out);
 }
 
 namespace {
@@ -63,9 +65,10 @@ hp_status load_file_locked(const char* path) {
   if (!f) return hp::fail(HP_EINVAL, "cannot open tuner cache %s", path);
   char key[256];
   long long k;
-  int vj, gj;
+  int mode, vj, gj, pw, opt;
   double us;
-  while (fscanf(f, "%255s %lld %d %d %lf", key, &k, &vj, &gj, &us) == 5) g_cache[key] = hp::Recipe{k, vj, gj, us};
+  while (fscanf(f, "%255s %d %lld %d %d %d %d %lf", key, &mode, &k, &vj, &gj, &pw, &opt, &us) == 8)
+    g_cache[key] = hp::Recipe{mode, k, vj, gj, pw, opt, us};
   fclose(f);
   return HP_OK;
 }
@@ -102,55 +105,90 @@ std::string tune_key(const hp_nest* n) {
 bool apply_recipe(const hp_nest* n, const Recipe& r, int nw, hp_nest* shaped, hp_level_map* map) {
   int p;
   int64_t block;
-  if (r.k <= 0 || !single_segment(n, &p, &block)) return false;
-  if (block % r.k != 0 || p + 2 > HP_MAX_DEPTH) return false;
-  if (r.vj < 1 || r.vj > 64 || (r.vj & (r.vj - 1)) || r.gj < 1) return false;
+  if (r.mode == 0 || !single_segment(n, &p, &block)) return false;
   const int op = n->op[p];
   memset(shaped, 0, sizeof *shaped);
+  memset(map, 0, sizeof *map);
   shaped->dtype = n->dtype;
   for (int l = 0; l < p; ++l) {
     shaped->extent[l] = n->extent[l];
     shaped->op[l] = HP_OP_NONE;
+    map->scopes[l] = HP_SCOPE_G;
   }
-  shaped->extent[p] = block / r.k;
-  shaped->op[p] = op;
-  shaped->extent[p + 1] = r.k;
-  shaped->op[p + 1] = op;
-  shaped->depth = p + 2;
-  memset(map, 0, sizeof *map);
-  for (int l = 0; l < p; ++l) map->scopes[l] = HP_SCOPE_G;
-  uint32_t sj = HP_SCOPE_W;
-  if (r.gj > 1) sj |= HP_SCOPE_G;
-  if (r.vj > 1) sj |= HP_SCOPE_V;
-  map->scopes[p] = sj;
-  map->units[p][HP_AXIS_W] = (uint32_t)nw;
-  if (r.gj > 1) map->units[p][HP_AXIS_G] = (uint32_t)r.gj;
-  if (r.vj > 1) map->units[p][HP_AXIS_V] = (uint32_t)r.vj;
-  map->scopes[p + 1] = HP_SCOPE_V;
-  map->units[p + 1][HP_AXIS_V] = (uint32_t)(64 / r.vj);
-  return true;
+  if (r.mode == 1) {
+    if (r.k <= 0 || block % r.k != 0 || p + 2 > HP_MAX_DEPTH) return false;
+    if (r.vj < 1 || r.vj > 64 || (r.vj & (r.vj - 1)) || r.gj < 1) return false;
+    shaped->extent[p] = block / r.k;
+    shaped->op[p] = op;
+    shaped->extent[p + 1] = r.k;
+    shaped->op[p + 1] = op;
+    shaped->depth = p + 2;
+    uint32_t sj = HP_SCOPE_W;
+    if (r.gj > 1) sj |= HP_SCOPE_G;
+    if (r.vj > 1) sj |= HP_SCOPE_V;
+    map->scopes[p] = sj;
+    map->units[p][HP_AXIS_W] = (uint32_t)nw;
+    if (r.gj > 1) map->units[p][HP_AXIS_G] = (uint32_t)r.gj;
+    if (r.vj > 1) map->units[p][HP_AXIS_V] = (uint32_t)r.vj;
+    map->scopes[p + 1] = HP_SCOPE_V;
+    map->units[p + 1][HP_AXIS_V] = (uint32_t)(64 / r.vj);
+    return true;
+  }
+  if (r.mode == 2) {
+    if (p < 1 || r.pw < 1 || r.pw > 64 || (r.pw & (r.pw - 1)) || r.opt < 1) return false;
+    const int64_t eo = n->extent[p - 1];
+    shaped->extent[p] = block;
+    shaped->op[p] = op;
+    shaped->depth = p + 1;
+    const int64_t parts = 64 / r.pw;
+    int64_t g = (eo + r.opt - 1) / r.opt;
+    if (g < 1) g = 1;
+    map->scopes[p - 1] = HP_SCOPE_G | HP_SCOPE_W | (parts > 1 ? HP_SCOPE_V : 0u);
+    map->units[p - 1][HP_AXIS_G] = (uint32_t)g;
+    map->units[p - 1][HP_AXIS_W] = (uint32_t)nw;
+    if (parts > 1) map->units[p - 1][HP_AXIS_V] = (uint32_t)parts;
+    map->scopes[p] = HP_SCOPE_V;
+    map->units[p][HP_AXIS_V] = (uint32_t)r.pw;
+    return true;
+  }
+  return false;
+}
+
+Recipe default_recipe(const hp_nest* n, int nw) {
+  Recipe r{0, 0, 1, 1, 64, 1, 0.0};
+  int p;
+  int64_t block;
+  if (!single_segment(n, &p, &block) || p < 1) return r;
+  const int es = elem_bytes(n->dtype);
+  const int64_t bytes = block * es;
+  if (bytes >= (16 << 10)) return r;  // large blocks: the automatic map splits them
+  const int c = (block % (16 / es) == 0) ? 16 / es : 1;
+  int64_t lanes = (block + c - 1) / c;
+  int pw = 1;
+  while (pw < lanes && pw < 64) pw *= 2;
+  const int64_t per_pass = (64 / pw) * (int64_t)nw;
+  int64_t opt = ((32 << 10) / (bytes > 0 ? bytes : 1)) / per_pass * per_pass;
+  if (opt < per_pass) opt = per_pass;
+  const int64_t eo = n->extent[p - 1];
+  if (opt > eo) opt = (eo + per_pass - 1) / per_pass * per_pass;
+  r.mode = 2;
+  r.pw = pw;
+  r.opt = (int32_t)(opt > 0x7FFFFFFF ? 0x7FFFFFFF : opt);
+  return r;
 }
 
 hp_status plan_for_batch(const hp_nest* nest, uint32_t flags, bool use_tuner, int nw, Lowered* out) {
   if (!nest) return fail(HP_EINVAL, "null nest");
+  Recipe r = default_recipe(nest, nw);
   if (use_tuner) {
-    Recipe r{0, 1, 1, 0.0};
-    bool have = false;
-    {
-      std::lock_guard<std::mutex> lk(g_mu);
-      load_env_locked();
-      auto it = g_cache.find(tune_key(nest));
-      if (it != g_cache.end()) {
-        r = it->second;
-        have = true;
-      }
-    }
-    hp_nest shaped;
-    hp_level_map m;
-    if (have && apply_recipe(nest, r, nw, &shaped, &m)) {
-      if (lower(&shaped, &m, flags, out, nw) == HP_OK) return HP_OK;
-    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_env_locked();
+    auto it = g_cache.find(tune_key(nest));
+    if (it != g_cache.end()) r = it->second;
   }
+  hp_nest shaped;
+  hp_level_map m;
+  if (apply_recipe(nest, r, nw, &shaped, &m) && lower(&shaped, &m, flags, out, nw) == HP_OK) return HP_OK;
   return lower(nest, nullptr, flags, out, nw);
 }
 
@@ -172,8 +210,8 @@ extern "C" hp_status hp_tune_cache_save(const char* path) {
   FILE* f = fopen(path, "w");
   if (!f) return hp::fail(HP_EINVAL, "cannot write %s", path);
   for (const auto& kv : g_cache)
-    fprintf(f, "%s %lld %d %d %.3f\n", kv.first.c_str(), (long long)kv.second.k, kv.second.vj, kv.second.gj,
-            kv.second.us);
+    fprintf(f, "%s %d %lld %d %d %d %d %.3f\n", kv.first.c_str(), kv.second.mode, (long long)kv.second.k,
+            kv.second.vj, kv.second.gj, kv.second.pw, kv.second.opt, kv.second.us);
   fclose(f);
   return HP_OK;
 }
@@ -240,6 +278,44 @@ hp_status time_candidate(const hp::Lowered& L, const void* in, void* out, int re
   return HP_OK;
 }
 
+// Throughput of a candidate inside a batch: R replicas of the plan (distinct input
+// and output slots) as one persistent launch; returns the median time per nest.
+// This is the figure that matters when the nest shares the device with others.
+hp_status time_candidate_batch(const hp::Lowered& L, int R, unsigned char* in, size_t in_stride, unsigned char* out,
+                               size_t out_stride, int reps, hipStream_t st, double* us) {
+  std::vector<hp::Lowered> plans((size_t)R, L);
+  hp_batch_s* b = nullptr;
+  hp_status s = hp::batch_from_plans(plans, 0, &b);
+  if (s != HP_OK) return s;
+  std::vector<const void*> ins((size_t)R);
+  std::vector<void*> outs((size_t)R);
+  for (int i = 0; i < R; ++i) {
+    ins[(size_t)i] = in + (size_t)i * in_stride;
+    outs[(size_t)i] = out + (size_t)i * out_stride;
+  }
+  s = hp_batch_set_io(b, ins.data(), outs.data());
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  std::vector<float> t;
+  for (int r = 0; r < reps + 2 && s == HP_OK; ++r) {
+    (void)hipEventRecord(e0, st);
+    s = hp_batch_run(b, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) s = hp::fail(HP_EDEVICE, "tuner batch run failed");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (r >= 2) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hp_batch_destroy(b);
+  if (s != HP_OK) return s;
+  std::sort(t.begin(), t.end());
+  *us = t.empty() ? 0.0 : 1e3 * (double)t[t.size() / 2] / (double)R;
+  return HP_OK;
+}
+
 }  // namespace
 
 extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t reps, double* best_us,
@@ -249,14 +325,20 @@ extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t r
   int p;
   int64_t block;
   Lowered L0;
-  hp_status s = lower(nest, nullptr, flags, &L0, kBatchWaves);
+  hp_status s = plan_for_batch(nest, flags, false, kBatchWaves, &L0);
   if (s != HP_OK) return s;
   const bool tunable = single_segment(nest, &p, &block);
-  // device buffers of the nest's size (values do not change the kernels' timing)
-  void* in = nullptr;
-  void* out = nullptr;
-  if (hipMalloc(&in, L0.info.in_bytes + 16) != hipSuccess) return fail(HP_ENOMEM, "tuner input allocation");
-  if (hipMemset(in, 0, L0.info.in_bytes + 16) != hipSuccess || hipMalloc(&out, L0.info.out_bytes + 16) != hipSuccess) {
+  // device buffers for R replicas of the nest (values do not change the kernels' timing)
+  const size_t in_stride = (L0.info.in_bytes + 255) / 256 * 256;
+  const size_t out_stride = (L0.info.out_bytes + 255) / 256 * 256;
+  int R = (int)((size_t)(64 << 20) / in_stride);
+  if (R < 1) R = 1;
+  if (R > 2048) R = 2048;
+  unsigned char* in = nullptr;
+  unsigned char* out = nullptr;
+  if (hipMalloc((void**)&in, in_stride * (size_t)R) != hipSuccess) return fail(HP_ENOMEM, "tuner input allocation");
+  if (hipMemset(in, 0, in_stride * (size_t)R) != hipSuccess ||
+      hipMalloc((void**)&out, out_stride * (size_t)R) != hipSuccess) {
     (void)hipFree(in);
     return fail(HP_ENOMEM, "tuner output allocation");
   }
@@ -267,16 +349,31 @@ extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t r
     return fail(HP_EDEVICE, "tuner stream");
   }
   double t_auto = 0;
-  s = time_candidate(L0, in, out, reps, st, &t_auto);
-  Recipe best{0, 1, 1, t_auto};
+  s = time_candidate_batch(L0, R, in, in_stride, out, out_stride, reps, st, &t_auto);
+  Recipe best{0, 0, 1, 1, 64, 1, t_auto};
+  auto consider = [&](const Recipe& r) {
+    hp_nest shaped;
+    hp_level_map m;
+    Lowered L;
+    if (!apply_recipe(nest, r, kBatchWaves, &shaped, &m)) return;
+    if (lower(&shaped, &m, flags, &L, kBatchWaves) != HP_OK) return;
+    double us = 0;
+    if (time_candidate_batch(L, R, in, in_stride, out, out_stride, reps, st, &us) != HP_OK) return;
+    if (us < best.us * 0.98) {
+      best = r;
+      best.us = us;
+    }
+  };
   if (s == HP_OK && tunable) {
     const int c = 16 / elem_bytes(nest->dtype);
-    std::vector<int64_t> ks;
-    for (int64_t k = c; k <= block && k <= (int64_t)c * 1024; k *= 2)
-      if (block % k == 0) ks.push_back(k);
     int64_t outs = 1;
     for (int l = 0; l < p; ++l) outs *= nest->extent[l];
-    for (int64_t k : ks) {
+    // default recipe first, so a tie keeps it
+    const Recipe d = default_recipe(nest, kBatchWaves);
+    if (d.mode != 0) consider(d);
+    // mode 1: (J, K) rows
+    for (int64_t k = c; k <= block && k <= (int64_t)c * 1024; k *= 2) {
+      if (block % k != 0) continue;
       for (int vj = 1; vj <= 16; vj *= 2) {
         if ((64 / vj) * c > 4 * k) continue;  // most lanes of a row would idle
         const int64_t J = block / k;
@@ -284,18 +381,19 @@ extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t r
         for (int gj = 1; gj <= 512; gj *= 2) {
           if ((int64_t)gj * kBatchWaves * vj > J) break;
           if (outs * gj > 65536) break;
-          Recipe r{k, vj, gj, 0.0};
-          hp_nest shaped;
-          hp_level_map m;
-          Lowered L;
-          if (!apply_recipe(nest, r, kBatchWaves, &shaped, &m)) continue;
-          if (lower(&shaped, &m, flags, &L, kBatchWaves) != HP_OK) continue;
-          double us = 0;
-          if (time_candidate(L, in, out, reps, st, &us) != HP_OK) continue;
-          if (us < best.us * 0.98) {
-            best = r;
-            best.us = us;
-          }
+          consider(Recipe{1, k, vj, gj, 64, 1, 0.0});
+        }
+      }
+    }
+    // mode 2: many outputs per task
+    if (p >= 1) {
+      for (int pw = 1; pw <= 64; pw *= 2) {
+        if ((int64_t)pw * c > 4 * block && pw > 1) break;
+        const int64_t per_pass = (64 / pw) * (int64_t)kBatchWaves;
+        for (int64_t mult = 1; mult <= 64; mult *= 2) {
+          const int64_t opt = per_pass * mult;
+          if (opt > 2 * nest->extent[p - 1] && mult > 1) break;
+          consider(Recipe{2, 0, 1, 1, pw, (int32_t)opt, 0.0});
         }
       }
     }

@@ -130,3 +130,19 @@ def test_scalar_chunk_when_extent_is_ragged():
     assert hp.inspect((4, 7), ("NONE", "SUM"), hp.F32)["chunk"] == 1
     assert hp.inspect((4, 8), ("NONE", "SUM"), hp.BF16)["chunk"] == 8
     assert hp.inspect((4, 8), ("NONE", "SUM"), hp.F32, flags=hp.FLAG_SCALAR)["chunk"] == 1
+
+
+def test_batch_plans_are_wave_tasks_of_useful_size():
+    import numpy as np
+
+    import workloads
+    bw = workloads.c4_batch(n=2000)
+    nests = [(n.extents, n.ops, n.dtype) for n in bw.nests]
+    infos = hp.batch_inspect(nests, 0x200)  # automatic maps, no tuner cache
+    assert all(i["waves"] == 1 for i in infos)
+    tasks = np.array([i["grid"] for i in infos])
+    nbytes = np.array([i["in_bytes"] for i in infos])
+    assert tasks.sum() < 4 * len(nests)           # small nests share tasks
+    assert (nbytes / tasks).mean() > 8 << 10       # tasks carry kilobytes, not bytes
+    for i, (ext, ops, dt) in zip(infos, nests):
+        assert i["n_out"] == ext[0]
