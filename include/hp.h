@@ -12,8 +12,9 @@
  * memory one level up).
  *
  * Hardware levels ("scopes") of gfx950, outermost first:
- *   G  the grid: workgroups; no barrier across them, combined through global
- *      memory with an atomic ticket (sections 1 and 3.2: teams have no barrier);
+ *   G  the grid: workgroups; no barrier across them (sections 1 and 3.2: teams
+ *      have no barrier), so each writes a partial to global memory and a second
+ *      small kernel folds the partials in index order;
  *   W  the workgroup: its wavefronts; combined through LDS and s_barrier;
  *   V  the wavefront: its 64 lanes; combined with DPP / swizzle / bpermute
  *      cross-lane moves.  V may be split between nested loops (partitions of
@@ -231,7 +232,7 @@ hp_status hp_tune_cache_size(int64_t* n);
  * later ones at most 64 times -- and launches a batch as soon as one of `streams`
  * slots is free and either max_batch requests wait, the oldest has waited
  * window_us, or the device is idle.  Batches of different slots overlap on the
- * device.  Request state (plans, task lists, partials, tickets) lives in the
+ * device.  Request state (plans, task lists, fold tasks, partials) lives in the
  * slot's device arena.  Each request keeps the plan it would get alone, so its
  * result does not depend on the batch it ran in.  Payloads are not copied: d_in
  * and d_out must stay valid until the request completes.

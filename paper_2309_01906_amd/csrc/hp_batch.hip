@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <new>
 #include <string>
 #include <vector>
@@ -48,6 +49,50 @@ __global__ void k_clear_counters(unsigned int* p, int n) {
 hp_status launch_clear(unsigned int* ctr, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_counters, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, n);
   if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "counter clear launch failed");
+  return HP_OK;
+}
+
+// Fold tasks: one wave each, grid-stride over the list.
+template <bool ONE>
+__device__ __forceinline__ void fold_body(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
+                                          unsigned char* const* wss, void* out1, const unsigned char* ws1) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int nwv = (int)(gridDim.x * (blockDim.x >> 6));
+  for (int t = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n; t += nwv) {
+    const FoldTask ft = tasks[t];
+    if (ONE) fold_task(plans[0], ft, out1, ws1, lane);
+    else fold_task(plans[ft.nest], ft, outs[ft.nest], wss[ft.nest], lane);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fold(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
+                                              unsigned char* const* wss) {
+  fold_body<false>(plans, tasks, n, outs, wss, nullptr, nullptr);
+}
+
+__global__ void __launch_bounds__(256) k_fold_one(const DevPlan* plan, const FoldTask* tasks, int n, void* out,
+                                                  const unsigned char* ws) {
+  fold_body<true>(plan, tasks, n, nullptr, nullptr, out, ws);
+}
+
+static unsigned fold_grid(int n) {
+  const int g = (n + 3) / 4;
+  return (unsigned)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
+}
+
+hp_status launch_fold(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
+                      unsigned char* const* wss, hipStream_t st) {
+  if (n <= 0) return HP_OK;
+  hipLaunchKernelGGL(k_fold, dim3(fold_grid(n)), dim3(256), 0, st, plans, tasks, n, outs, wss);
+  if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "fold launch failed");
+  return HP_OK;
+}
+
+hp_status launch_fold_one(const DevPlan* plan, const FoldTask* tasks, int n, void* out, const unsigned char* ws,
+                          hipStream_t st) {
+  if (n <= 0) return HP_OK;
+  hipLaunchKernelGGL(k_fold_one, dim3(fold_grid(n)), dim3(256), 0, st, plan, tasks, n, out, ws);
+  if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "fold launch failed");
   return HP_OK;
 }
 
@@ -103,8 +148,11 @@ struct hp_batch_s {
   void** d_out = nullptr;
   unsigned char** d_ws = nullptr;
   std::vector<unsigned char*> ws_ptrs;
-  void* arena = nullptr;  // tasks, counters, workspaces
+  void* arena = nullptr;  // tasks, counters, fold tasks, workspaces
   std::vector<Group> groups;
+  hp::FoldTask* d_fold = nullptr;  // in the arena
+  int n_fold = 0;
+  std::vector<int> fold_beg;      // nest i's fold tasks: [fold_beg[i], fold_beg[i + 1])
   bool io_set = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -211,6 +259,16 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
       return fail(HP_ETOOBIG, "batch group has %lld tasks, more than 2^31 - 1", ntask[g]);
     }
   }
+  std::vector<hp::FoldTask> folds;
+  b->fold_beg.assign((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    b->fold_beg[(size_t)i] = (int)folds.size();
+    fold_tasks_of(b->plans[(size_t)i], (int)i, folds);
+  }
+  b->fold_beg[(size_t)n] = (int)folds.size();
+  b->n_fold = (int)folds.size();
+  const size_t fold_off = arena_bytes;
+  arena_bytes = align_up(arena_bytes + folds.size() * sizeof(hp::FoldTask), 256);
   std::vector<size_t> ws_off((size_t)n, 0);
   for (int64_t i = 0; i < n; ++i) {
     const size_t wb = b->infos[(size_t)i].workspace_bytes;
@@ -228,6 +286,8 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
   b->d_out = reinterpret_cast<void**>(const_cast<void**>(b->d_in + n));
   b->d_ws = reinterpret_cast<unsigned char**>(const_cast<void**>(b->d_in + 2 * n));
   std::vector<unsigned char> host_arena(arena_bytes, 0);
+  if (!folds.empty()) memcpy(host_arena.data() + fold_off, folds.data(), folds.size() * sizeof(hp::FoldTask));
+  b->d_fold = reinterpret_cast<hp::FoldTask*>((unsigned char*)b->arena + fold_off);
   b->ws_ptrs.assign((size_t)n, nullptr);
   for (int64_t i = 0; i < n; ++i)
     if (b->infos[(size_t)i].workspace_bytes) b->ws_ptrs[(size_t)i] = (unsigned char*)b->arena + ws_off[(size_t)i];
@@ -332,7 +392,7 @@ static hp_status launch_groups(hp_batch_s* b, hipStream_t st) {
     if (s == HP_OK) s = hp::launch_batch(G.family, G.chunk, A, G.grid, hp::kBatchGroupWaves, G.lds, st);
     if (s != HP_OK) return s;
   }
-  return HP_OK;
+  return hp::launch_fold(b->d_plans, b->d_fold, b->n_fold, b->d_out, b->d_ws, st);
 }
 
 static hp_status capture(hp_batch_s* b, bool each, hipGraph_t* graph, hipGraphExec_t* exec);
@@ -355,6 +415,13 @@ extern "C" hp_status hp_batch_run(hp_batch_t b, void* stream) {
   return launch_groups(b, st);
 }
 
+// The fold kernel of nest i alone (what hp_run launches after a grid-split nest).
+static hp_status launch_fold_of(hp_batch_s* b, int64_t i, hipStream_t st) {
+  const int f0 = b->fold_beg[(size_t)i], f1 = b->fold_beg[(size_t)i + 1];
+  if (f1 == f0) return HP_OK;
+  return hp::launch_fold(b->d_plans, b->d_fold + f0, f1 - f0, b->d_out, b->d_ws, st);
+}
+
 // Baseline: the same plans, one single-nest launch per nest (optionally replayed
 // from one graph holding all of those launches).
 static hp_status launch_each(hp_batch_s* b, hipStream_t st) {
@@ -366,6 +433,7 @@ static hp_status launch_each(hp_batch_s* b, hipStream_t st) {
   for (int64_t i = 0; i < b->n; ++i) {
     hp_status s = hp::launch_single(b->plans[(size_t)i], b->d_plans + i, in[(size_t)i], out[(size_t)i],
                                     b->ws_ptrs[(size_t)i], b->infos[(size_t)i].lds_bytes, st);
+    if (s == HP_OK) s = launch_fold_of(b, i, st);
     if (s != HP_OK) return s;
   }
   return HP_OK;
@@ -389,9 +457,11 @@ static hp_status capture(hp_batch_s* b, bool each, hipGraph_t* graph, hipGraphEx
       (void)hipStreamDestroy(cs);
       return hp::fail(HP_EDEVICE, "begin capture failed");
     }
-    for (int64_t i = 0; i < b->n && s == HP_OK; ++i)
+    for (int64_t i = 0; i < b->n && s == HP_OK; ++i) {
       s = hp::launch_single(b->plans[(size_t)i], b->d_plans + i, ins[(size_t)i], outs[(size_t)i],
                             b->ws_ptrs[(size_t)i], b->infos[(size_t)i].lds_bytes, cs);
+      if (s == HP_OK) s = launch_fold_of(b, i, cs);
+    }
   } else {
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipStreamDestroy(cs);

@@ -51,7 +51,7 @@ static int elem_bytes(int dt) { return dt == HP_BF16 ? 2 : 4; }
 // wavefront from the innermost level outward (shuffles are the cheapest combine),
 // then the waves of a workgroup (LDS + barrier), then, when the outputs alone do
 // not give the chip enough workgroups, the outermost reducing level is also split
-// over the grid (atomic ticket combine).
+// over the grid (partials folded by a second kernel).
 static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, int force_nw) {
   const int d = n->depth;
   memset(m, 0, sizeof *m);
@@ -464,7 +464,7 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
   I.waves = dp.nw;
   I.chunk = chunk_last;
   I.gsplit = dp.gsplit;
-  I.workspace_bytes = dp.gsplit > 1 ? (size_t)dp.n_out * dp.gsplit * kSlotBytes + (size_t)dp.n_out * 4 + 256 : 0;
+  I.workspace_bytes = dp.gsplit > 1 ? (size_t)dp.n_out * dp.gsplit * kSlotBytes : 0;
   {
     size_t slots = (size_t)dp.nw * dp.lds_slot_lanes * kSlotBytes;
     size_t gcomb = (size_t)dp.nw * 32;

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <vector>
 
 #include "hp_internal.h"
 
@@ -9,7 +10,9 @@
 
 struct hp_plan_s {
   hp::DevPlan dp;        // host copy: launch geometry
-  hp::DevPlan* d_dp;     // device copy: read by the kernels
+  hp::DevPlan* d_dp;     // device copy: read by the kernels, followed by the fold tasks
+  hp::FoldTask* d_fold;  // grid combine: the fold kernel's tasks (n_fold of them)
+  int n_fold;
   hp_plan_info info;
   void* ws;
   int device;
@@ -27,15 +30,23 @@ extern "C" hp_status hp_plan(const hp_nest* nest, const hp_level_map* map, uint3
   p->info = L.info;
   p->ws = nullptr;
   p->d_dp = nullptr;
+  p->d_fold = nullptr;
+  std::vector<hp::FoldTask> folds;
+  hp::fold_tasks_of(p->dp, 0, folds);
+  p->n_fold = (int)folds.size();
+  const size_t plan_bytes = (sizeof(hp::DevPlan) + 255) / 256 * 256;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return hp::fail(HP_EDEVICE, "no HIP device");
   }
-  if (hipMalloc(&p->d_dp, sizeof(hp::DevPlan)) != hipSuccess) {
+  if (hipMalloc(&p->d_dp, plan_bytes + folds.size() * sizeof(hp::FoldTask)) != hipSuccess) {
     delete p;
     return hp::fail(HP_ENOMEM, "device plan allocation failed");
   }
-  if (hipMemcpy(p->d_dp, &p->dp, sizeof(hp::DevPlan), hipMemcpyHostToDevice) != hipSuccess) {
+  p->d_fold = reinterpret_cast<hp::FoldTask*>(reinterpret_cast<unsigned char*>(p->d_dp) + plan_bytes);
+  if (hipMemcpy(p->d_dp, &p->dp, sizeof(hp::DevPlan), hipMemcpyHostToDevice) != hipSuccess ||
+      (!folds.empty() &&
+       hipMemcpy(p->d_fold, folds.data(), folds.size() * sizeof(hp::FoldTask), hipMemcpyHostToDevice) != hipSuccess)) {
     (void)hipFree(p->d_dp);
     delete p;
     return hp::fail(HP_EDEVICE, "device plan upload failed");
@@ -46,7 +57,7 @@ extern "C" hp_status hp_plan(const hp_nest* nest, const hp_level_map* map, uint3
       delete p;
       return hp::fail(HP_ENOMEM, "workspace allocation of %zu bytes failed", L.info.workspace_bytes);
     }
-    // partials need no clearing; tickets start at zero and every run leaves them at zero
+    // every run writes all partials before the fold reads them; cleared for tidiness
     if (hipMemset(p->ws, 0, p->info.workspace_bytes) != hipSuccess) {
       (void)hipFree(p->ws);
       (void)hipFree(p->d_dp);
@@ -74,11 +85,16 @@ extern "C" hp_status hp_run(hp_plan_t plan, const void* d_in, void* d_out, void*
   if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
     return hp::fail(HP_EINVAL, "plan was made on device %d, current device is %d", plan->device, dev);
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hp_status s;
   switch (plan->dp.dtype) {
-    case HP_F32: return hp::launch_nest_f32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st);
-    case HP_BF16: return hp::launch_nest_bf16(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st);
-    default: return hp::launch_nest_i32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st);
+    case HP_F32: s = hp::launch_nest_f32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st); break;
+    case HP_BF16: s = hp::launch_nest_bf16(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st); break;
+    default: s = hp::launch_nest_i32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st); break;
   }
+  if (s == HP_OK && plan->n_fold)
+    s = hp::launch_fold_one(plan->d_dp, plan->d_fold, plan->n_fold, d_out,
+                            reinterpret_cast<const unsigned char*>(plan->ws), st);
+  return s;
 }
 
 extern "C" hp_status hp_destroy(hp_plan_t plan) {

@@ -127,6 +127,10 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
     ctr_off[g] = off;
     off = align_up(off + kCtrWords * sizeof(unsigned int), 256);
   }
+  std::vector<FoldTask> folds;
+  for (int64_t i = 0; i < n; ++i) fold_tasks_of(rs[(size_t)i]->L.dp, (int)i, folds);
+  const size_t fold_off = off;
+  off = align_up(off + folds.size() * sizeof(FoldTask), 256);
   const size_t ws_begin = off;
   std::vector<size_t> ws_off((size_t)n, 0);
   for (int64_t i = 0; i < n; ++i) {
@@ -180,11 +184,11 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
     deal_tasks(ordered.data(), (int)ntask[g], grid[g], reinterpret_cast<int2*>(h + task_off[g]), &args[g]);
     memset(h + ctr_off[g], 0, kCtrWords * sizeof(unsigned int));
   }
-  // upload descriptors (not the workspaces), clear the workspaces (tickets start at 0)
+  if (!folds.empty()) memcpy(h + fold_off, folds.data(), folds.size() * sizeof(FoldTask));
+  // upload the descriptors; the workspaces need no clearing (every partial is written
+  // before the fold kernel reads it)
   if (hipMemcpyAsync(d, h, ws_begin, hipMemcpyHostToDevice, slot.st) != hipSuccess)
     return fail(HP_EDEVICE, "batch upload failed");
-  if (off > ws_begin && hipMemsetAsync(d + ws_begin, 0, off - ws_begin, slot.st) != hipSuccess)
-    return fail(HP_EDEVICE, "workspace clear failed");
   for (size_t g = 0; g < keys.size(); ++g) {
     BatchArgs A = args[g];
     A.plans = reinterpret_cast<const DevPlan*>(d + plans_off);
@@ -194,6 +198,13 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
     A.outs = reinterpret_cast<void* const*>(d + ptr_off) + n;
     A.wss = reinterpret_cast<unsigned char* const*>(d + ptr_off) + 2 * n;
     hp_status s = launch_batch(keys[g].first, keys[g].second, A, grid[g], kBatchGroupWaves, lds, slot.st);
+    if (s != HP_OK) return s;
+  }
+  if (!folds.empty()) {
+    hp_status s = launch_fold(reinterpret_cast<const DevPlan*>(d + plans_off),
+                              reinterpret_cast<const FoldTask*>(d + fold_off), (int)folds.size(),
+                              reinterpret_cast<void* const*>(d + ptr_off) + n,
+                              reinterpret_cast<unsigned char* const*>(d + ptr_off) + 2 * n, slot.st);
     if (s != HP_OK) return s;
   }
   if (hipEventRecord(slot.ev, slot.st) != hipSuccess) return fail(HP_EDEVICE, "event record failed");
