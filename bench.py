@@ -67,7 +67,7 @@ def time_plan(plan, dev_in, out, steps, warmup, stream):
 def traffic_from_profiles(per_launch_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel sources; else None."""
-    p = os.path.join(ROOT, "profiles", "c2_nest_counters.json")
+    p = COUNTERS_JSON
     if not os.path.exists(p):
         return None
     try:
@@ -77,6 +77,47 @@ def traffic_from_profiles(per_launch_bytes):
     if d.get("kernel_hash") != kernel_hash():
         return None
     return d.get("traffic_bytes_per_launch")
+
+
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "c2_nest_counters.json")
+
+
+def ingest_counters(fetch_csv, write_csv, kernel, nbytes, copy_bytes=1 << 30):
+    """Turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of a `bench.py --copy-calib` run into HBM bytes
+    per launch of `kernel`.  Each counter is scaled by what it reads for the 1 GiB
+    device copy of the same run (reads 1 GiB, writes 1 GiB)."""
+    import csv
+
+    def rows(path, counter):
+        out = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+        return out
+
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rs = rows(path, counter)
+        ks = [v for n, _, v in rs if kernel in n]
+        copies = [(g, v) for n, g, v in rs if "copyBuffer" in n]
+        if not ks or not copies:
+            raise SystemExit(f"{path}: no {counter} rows for {kernel} or for the calibration copy")
+        calib = max(copies)[1]  # the largest copy dispatch is the 1 GiB calibration copy
+        scale = copy_bytes / (calib * 1024.0)
+        res[counter] = {"kib_per_dispatch": round(sum(ks) / len(ks), 3), "dispatches": len(ks),
+                        "copy_kib": calib, "scale": round(scale, 6),
+                        "bytes_per_launch": round(sum(ks) / len(ks) * 1024.0 * scale)}
+    traffic = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    d = {"kernel": kernel, "kernel_hash": kernel_hash(), "algorithmic_bytes_per_launch": nbytes,
+         "traffic_bytes_per_launch": traffic, "traffic_over_algorithmic": round(traffic / nbytes, 5),
+         "counters": res, "calibration": f"device copy of {copy_bytes} bytes (reads and writes that many)"}
+    os.makedirs(os.path.dirname(COUNTERS_JSON), exist_ok=True)
+    with open(COUNTERS_JSON, "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(d))
 
 
 def cpu_baseline(x_host, ext, ops, got_rows):
@@ -260,7 +301,16 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="host only: write the traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        import paper_2309_01906_amd as hp
+        import workloads
+        info = hp.inspect(workloads.C2.extents, workloads.C2.ops, workloads.C2.dtype)
+        ingest_counters(args.ingest_counters[0], args.ingest_counters[1], info["kernel_name"],
+                        info["in_bytes"] + info["out_bytes"])
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -306,7 +356,7 @@ def main():
         "p50_us": round(pct(ev_ms, 50) * 1e3, 2), "p99_us": round(pct(ev_ms, 99) * 1e3, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic_from_profiles(nbytes),
-                     "kernel": "hp::k_nest_f32<4,4>", "algorithmic_bytes_per_launch": nbytes,
+                     "kernel": plan.info["kernel_name"], "algorithmic_bytes_per_launch": nbytes,
                      "kernel_hash": kernel_hash()},
     }
     if not args.no_cpu_baseline:

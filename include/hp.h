@@ -122,7 +122,19 @@ typedef struct hp_plan_info {
   uint32_t units[HP_MAX_DEPTH][3];
   int64_t strips[HP_MAX_DEPTH];    /* serial strips per level per unit */
   int32_t nseg;                    /* reducing segments (runs of levels combined as one) */
+  int32_t kernel;                  /* hp_kernel: the kernel variant hp_run launches */
 } hp_plan_info;
+
+/* Kernel variants (hp_plan_info.kernel).  Every variant runs the same level
+ * mapping; they differ in which code paths are compiled in. */
+typedef enum hp_kernel {
+  HP_KERNEL_LEAN = 0,     /* float, depth <= 4, at most one strided inner dim, <= 8 waves, vector chunk */
+  HP_KERNEL_GENERIC4 = 1, /* float, depth <= 4 */
+  HP_KERNEL_GENERIC8 = 2, /* float, depth <= 8 */
+  HP_KERNEL_INT_FLAT = 3, /* int32, depth <= 4, one reducing segment */
+  HP_KERNEL_INT_SEG = 4,  /* int32, depth <= 4, up to three segments */
+  HP_KERNEL_INT_DEEP = 5  /* int32, anything else */
+} hp_kernel;
 
 typedef struct hp_plan_s* hp_plan_t;
 

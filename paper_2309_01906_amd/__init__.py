@@ -51,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("grid", ctypes.c_int64), ("waves", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("gsplit", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t), ("lds_bytes", ctypes.c_size_t),
                 ("scopes", ctypes.c_uint32 * MAX_DEPTH), ("units", (ctypes.c_uint32 * 3) * MAX_DEPTH),
-                ("strips", ctypes.c_int64 * MAX_DEPTH), ("nseg", ctypes.c_int32)]
+                ("strips", ctypes.c_int64 * MAX_DEPTH), ("nseg", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
 
 
 _lib = None
@@ -123,6 +124,21 @@ def make_map(level_map) -> LevelMap | None:
     return m
 
 
+KERNEL_LEAN, KERNEL_GENERIC4, KERNEL_GENERIC8, KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP = range(6)
+
+
+def kernel_name(inf: PlanInfo) -> str:
+    """Symbol of the kernel hp_run launches for a plan (as profilers print it)."""
+    c = inf.chunk
+    if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP):
+        kind = {KERNEL_INT_FLAT: "flat", KERNEL_INT_SEG: "seg", KERNEL_INT_DEEP: "deep"}[inf.kernel]
+        return f"hp::k_nest_i32_{kind}<{c}>"
+    t = "bf16" if inf.in_bytes == 2 * inf.in_elems else "f32"
+    if inf.kernel == KERNEL_LEAN:
+        return f"hp::k_nest_{t}_lean<{c}>"
+    return f"hp::k_nest_{t}<{c}, {4 if inf.kernel == KERNEL_GENERIC4 else MAX_DEPTH}>"
+
+
 def _info_dict(inf: PlanInfo) -> dict:
     d = inf.depth
     names = "GWVL"
@@ -130,7 +146,7 @@ def _info_dict(inf: PlanInfo) -> dict:
         "depth": d, "out_dtype": inf.out_dtype, "n_out": inf.n_out, "out_bytes": inf.out_bytes,
         "in_elems": inf.in_elems, "in_bytes": inf.in_bytes, "grid": inf.grid, "waves": inf.waves,
         "chunk": inf.chunk, "gsplit": inf.gsplit, "workspace_bytes": inf.workspace_bytes,
-        "lds_bytes": inf.lds_bytes, "nseg": inf.nseg,
+        "lds_bytes": inf.lds_bytes, "nseg": inf.nseg, "kernel": inf.kernel, "kernel_name": kernel_name(inf),
         "map": ["".join(names[b] for b in range(4) if inf.scopes[i] >> b & 1) for i in range(d)],
         "units": [tuple(inf.units[i][a] for a in range(3)) for i in range(d)],
         "strips": [inf.strips[i] for i in range(d)],

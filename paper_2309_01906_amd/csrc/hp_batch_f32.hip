@@ -1,5 +1,5 @@
 // Persistent batched kernels: fp32 nests.
-#include "hp_nest.h"
+#include "hp_batch_dev.h"
 
 namespace hp {
 

@@ -1,5 +1,5 @@
 // Persistent batched kernels: int32 nests with up to three segments, depth <= 4.
-#include "hp_nest.h"
+#include "hp_batch_dev.h"
 
 namespace hp {
 

@@ -1,5 +1,5 @@
 // Persistent batched kernels: int32 nests of any depth and segment count.
-#include "hp_nest.h"
+#include "hp_batch_dev.h"
 
 namespace hp {
 

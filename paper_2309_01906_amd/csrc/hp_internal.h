@@ -80,7 +80,7 @@ struct alignas(16) DevPlan {
   int32_t a;                        // first level of the innermost segment
   int32_t nid;                      // number of inner dims
   int32_t last_dim_is_last_level;   // the innermost inner dim is level depth-1
-  int32_t pad2;
+  int32_t kernel;                   // hp_kernel variant
   int64_t inner_iters;              // product of strips over the innermost segment
   int64_t outer_iters;              // product of strips over reducing levels before it
   int64_t id_strips[kMaxDepth];

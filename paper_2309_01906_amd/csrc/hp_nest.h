@@ -30,7 +30,6 @@
 #include <stdint.h>
 
 #include <type_traits>
-#include <vector>
 
 #include "hp_internal.h"
 
@@ -142,37 +141,26 @@ struct IntT {
       default: return Acc{0, 0, 0};
     }
   }
+  // Merge carrier b into a.  Written without branches on op: op is uniform, and in
+  // the combine code a switch per call multiplies the scalar work and the code size;
+  // with a constant op (the element folds) the selects fold away.
+  // ARG: lexicographic (value, index), so ties keep the smaller index.
+  __device__ static __forceinline__ Acc merge(Acc a, Acc b, int op) {
+    const bool sum = op == HP_OP_SUM;
+    const bool keep = op == HP_OP_NONE;
+    const bool minlike = op == HP_OP_MIN || op == HP_OP_ARGMIN;
+    const bool arg = op == HP_OP_ARGMIN || op == HP_OP_ARGMAX;
+    const bool lt = b.v < a.v, gt = b.v > a.v;
+    const bool take = !sum && !keep && ((minlike ? lt : gt) || (arg && b.v == a.v && b.i < a.i));
+    Acc r;
+    r.v = sum ? (long long)((unsigned long long)a.v + (unsigned long long)b.v) : (take ? b.v : a.v);
+    r.i = take ? b.i : a.i;
+    r.pad = 0;
+    return r;
+  }
   // fold child value x with iteration index t into the carrier
   __device__ static __forceinline__ void add(Acc& a, long long x, long long t, int op) {
-    switch (op) {
-      case HP_OP_SUM: a.v = (long long)((unsigned long long)a.v + (unsigned long long)x); break;
-      case HP_OP_MIN: a.v = x < a.v ? x : a.v; break;
-      case HP_OP_MAX: a.v = x > a.v ? x : a.v; break;
-      case HP_OP_ARGMIN:
-        if (x < a.v || (x == a.v && (int)t < a.i)) {
-          a.v = x;
-          a.i = (int)t;
-        }
-        break;
-      case HP_OP_ARGMAX:
-        if (x > a.v || (x == a.v && (int)t < a.i)) {
-          a.v = x;
-          a.i = (int)t;
-        }
-        break;
-      default: break;
-    }
-  }
-  // lexicographic (value, index) for ARG: ties keep the smaller index
-  __device__ static __forceinline__ Acc merge(Acc a, Acc b, int op) {
-    switch (op) {
-      case HP_OP_SUM: a.v = (long long)((unsigned long long)a.v + (unsigned long long)b.v); return a;
-      case HP_OP_MIN: a.v = b.v < a.v ? b.v : a.v; return a;
-      case HP_OP_MAX: a.v = b.v > a.v ? b.v : a.v; return a;
-      case HP_OP_ARGMIN: return (b.v < a.v || (b.v == a.v && b.i < a.i)) ? b : a;
-      case HP_OP_ARGMAX: return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a;
-      default: return a;
-    }
+    a = merge(a, Acc{x, (int)t, 0}, op);
   }
   __device__ static __forceinline__ long long emit(Acc a, int op) {
     return (op == HP_OP_ARGMIN || op == HP_OP_ARGMAX) ? (long long)a.i : a.v;
@@ -583,6 +571,13 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
           if (vj) IntT::add(outer[j], IntT::emit(ai, P.seg[inner].op), t, Sp.op);
         }
       }
+      // common case: the innermost outer level has strips left, so no outer
+      // segment ends here
+      bool more = false;
+#pragma unroll
+      for (int m = 0; m < KD; ++m)
+        if (m == a_lv - 1 && m >= p) more = s[m] < P.lv[m].strips - 1;
+      if (more) return;
       int J = 0;
 #pragma unroll
       for (int m = 0; m < KD; ++m)
@@ -712,152 +707,6 @@ __device__ __forceinline__ DPair dpair_merge(DPair a, DPair b) {
   return DPair{s2, c - (s2 - s)};
 }
 
-// The grid combine.  Every workgroup of a grid-split nest writes its partial (one
-// slot per workgroup digit of the reducing levels) and a second, small kernel folds
-// the partials of each output once all workgroups are done.  The kernel boundary
-// makes the partials visible across the XCDs' L2 caches; an in-kernel "last
-// arriver" fold would need an agent-scope release and acquire per workgroup, which
-// write back and invalidate the whole L2 of an XCD each time.
-//
-// The fold order is fixed by the partial count G alone, never by how many threads
-// run it, so every launch form of a plan gives the same bits:
-//   floats, G <= kSeqFold: one lane adds s then c of partials 0, 1, ..., G-1 into
-//     an fp64 pair;
-//   floats, G > kSeqFold: lane k adds partials k, k+64, ... the same way and the 64
-//     pairs merge in a xor butterfly;
-//   integers: the operators are exact, associative and commutative (ARG keeps the
-//     smaller index on ties), so any order gives the same result; several grid-
-//     spanning segments are folded by one lane, digits in index order.
-constexpr long long kSeqFold = 16;
-
-__device__ __forceinline__ double fold_flt_seq(const char* part, long long G) {
-  DPair a{0.0, 0.0};
-  for (long long k = 0; k < G; ++k) {
-    const FAcc v = FloatT<float>::get(part, k);
-    dpair_add(a, (double)v.s);
-    dpair_add(a, (double)v.c);
-  }
-  return a.s + a.c;
-}
-
-// whole wave; every lane returns the result
-__device__ __forceinline__ double fold_flt_wave(const char* part, long long G, int lane) {
-  DPair a{0.0, 0.0};
-  for (long long k = lane; k < G; k += kWave) {
-    const FAcc v = FloatT<float>::get(part, k);
-    dpair_add(a, (double)v.s);
-    dpair_add(a, (double)v.c);
-  }
-#pragma unroll
-  for (int b = 0; b < 6; ++b) {
-    const DPair o{xor_move_d(a.s, 1 << b, lane), xor_move_d(a.c, 1 << b, lane)};
-    a = dpair_merge(a, o);
-  }
-  return a.s + a.c;
-}
-
-__device__ __forceinline__ long long fold_int_uniform_seq(const char* part, long long G, int op) {
-  IAcc a = IntT::identity(op);
-  for (long long k = 0; k < G; ++k) a = IntT::merge(a, IntT::get(part, k), op);
-  return IntT::emit(a, op);
-}
-
-// Several segments span workgroups: fold segment gq's partials, then apply the
-// outer segments' operators in nest order.  Outer segments are pure grid levels
-// with one iteration per workgroup, so their iteration index is the workgroup digit.
-template <int KD>
-__device__ __forceinline__ long long fold_int_nested(const DevPlan& P, const char* part) {
-  const int q = P.gq;
-  IAcc A[KD];
-  long long dg[KD];
-#pragma unroll
-  for (int j = 0; j < KD; ++j) {
-    A[j] = IntT::identity(j <= q ? P.seg[j].op : 0);
-    dg[j] = 0;
-  }
-  for (long long idx = 0; idx < P.gsplit; ++idx) {
-    const IAcc pv = IntT::get(part, idx);
-#pragma unroll
-    for (int j = 0; j < KD; ++j)
-      if (j == q) A[j] = IntT::merge(A[j], pv, P.seg[j].op);
-    bool carry = true;
-#pragma unroll
-    for (int j = KD - 1; j >= 0; --j) {
-      if (j <= q && carry) {
-        const DevSeg& S = P.seg[j];
-        if (dg[j] == (long long)S.gunits - 1) {
-          if (j > 0) {
-            const DevSeg& Sp = P.seg[j - 1];
-            long long rem = dg[j - 1];
-            bool valid = true;
-            long long t_last = 0;
-            for (int l = Sp.last; l >= Sp.first; --l) {
-              const long long gfl = P.lv[l].gf;
-              const long long t = rem % gfl;
-              rem /= gfl;
-              if (t >= P.lv[l].e) valid = false;
-              if (l == Sp.last) t_last = t;
-            }
-            if (valid) IntT::add(A[j - 1], IntT::emit(A[j], S.op), t_last, Sp.op);
-            A[j] = IntT::identity(S.op);
-          }
-          dg[j] = 0;
-        } else {
-          dg[j] += 1;
-          carry = false;
-        }
-      }
-    }
-  }
-  return IntT::emit(A[0], P.seg[0].op);
-}
-
-// A fold task covers outputs [o0, o0 + n) of one nest: with one lane per output
-// (n <= 64) when every output folds on one lane, else one output per wave.
-struct FoldTask {
-  int nest;
-  int o0;
-  int n;
-  int wave;  // 1: the whole wave folds output o0
-};
-
-// Whether outputs of plan P fold on one lane each.
-__host__ __device__ inline bool fold_on_lane(const DevPlan& P) {
-  return P.dtype != HP_F32 && P.dtype != HP_BF16 ? true : P.gsplit <= kSeqFold;
-}
-
-// One wave runs one fold task.
-__device__ __forceinline__ void fold_task(const DevPlan& P, const FoldTask& t, void* out, const unsigned char* ws,
-                                          int lane) {
-  const bool flt = P.dtype == HP_F32 || P.dtype == HP_BF16;
-  if (t.wave) {
-    const long long o = t.o0;
-    const char* part = reinterpret_cast<const char*>(ws) + o * P.gsplit * kSlotBytes;
-    const double v = fold_flt_wave(part, P.gsplit, lane);
-    if (lane == 0) store_flt(P, out, o, v);
-    return;
-  }
-  if (lane >= t.n) return;
-  const long long o = (long long)t.o0 + lane;
-  const char* part = reinterpret_cast<const char*>(ws) + o * P.gsplit * kSlotBytes;
-  if (flt) store_flt(P, out, o, fold_flt_seq(part, P.gsplit));
-  else if (P.gmode == GCOMB_UNIFORM) store_int(P, out, o, fold_int_uniform_seq(part, P.gsplit, P.seg[0].op));
-  else store_int(P, out, o, fold_int_nested<kMaxDepth>(P, part));
-}
-
-// Host side: the fold tasks of one plan (appended to v).
-inline void fold_tasks_of(const DevPlan& P, int nest, std::vector<FoldTask>& v) {
-  if (P.gmode == GCOMB_NONE || P.gsplit <= 1) return;
-  if (fold_on_lane(P)) {
-    for (long long o = 0; o < P.n_out; o += kWave) {
-      const long long n = P.n_out - o < kWave ? P.n_out - o : kWave;
-      v.push_back(FoldTask{nest, (int)o, (int)n, 0});
-    }
-  } else {
-    for (long long o = 0; o < P.n_out; ++o) v.push_back(FoldTask{nest, (int)o, 1, 1});
-  }
-}
-
 // ---------------------------------------------------------------------------
 // one workgroup
 
@@ -962,102 +811,6 @@ __device__ __forceinline__ uint32_t logical_group(const DevPlan& P, uint32_t b) 
   const uint32_t per = (uint32_t)P.grid >> 3;  // grid % 8 == 0 when xcd is set
   return (b & 7u) * per + (b >> 3);
 }
-
-// Persistent batched kernels: workers pop (nest, workgroup) tasks with atomic
-// counters -- a dynamic schedule on the grid level.  The tasks are dealt, largest
-// first, into kQueues queues with one counter each; workgroup b takes from queue
-// b % kQueues, which is the XCD the hardware places it on, so the counters are
-// contended by one XCD each instead of the whole chip.  The counters are cleared by
-// a separate small kernel before every run, so a run can be replayed from a graph.
-constexpr int kQueues = 8;
-constexpr int kCtrStride = 64;  // counters 256 bytes apart
-
-struct BatchArgs {
-  const DevPlan* plans;        // one plan per nest
-  const int2* tasks;           // (nest, logical workgroup), queue by queue
-  unsigned int* ctr;           // kQueues counters, kCtrStride apart
-  const void* const* ins;      // per nest
-  void* const* outs;           // per nest
-  unsigned char* const* wss;   // per nest (grid-combine workspace, may be null)
-  int qbeg[kQueues + 1];       // queue q holds tasks [qbeg[q], qbeg[q+1])
-  int per_pop;                 // tasks taken per atomic
-};
-
-// Wave tasks: every wavefront of the workgroup is an independent worker running
-// one-wave plans (no workgroup barrier), with its own slice of LDS.  The task's
-// plan is first copied into that slice, so the kernel reads it from LDS instead of
-// with vector loads that would queue behind the data stream.  The next task index
-// is taken before the current task runs, so the atomic's latency overlaps it.
-constexpr int kPlanLdsBytes = (int)((sizeof(DevPlan) + 255) / 256 * 256);
-constexpr int kWaveLdsBytes = kPlanLdsBytes + 256;
-static_assert(sizeof(DevPlan) % 16 == 0, "plans are copied in 16-byte words");
-
-template <class T, int C, int NS, int U, int KD, bool PF = true>
-__device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
-  const int w = (int)(threadIdx.x >> 6);
-  const int lane = (int)(threadIdx.x & 63);
-  char* mine = lds + w * kWaveLdsBytes;
-  DevPlan* plan = reinterpret_cast<DevPlan*>(mine);
-  char* scratch = mine + kPlanLdsBytes;
-  const int q = (int)(blockIdx.x % kQueues);
-  const int qb = B.qbeg[q], qe = B.qbeg[q + 1];
-  const int k = B.per_pop;
-  unsigned int* ctr = B.ctr + q * kCtrStride;
-  auto pop = [&]() -> int {
-    unsigned int v = 0;
-    if (lane == 0) v = __hip_atomic_fetch_add(ctr, (unsigned int)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return qb + __builtin_amdgcn_readfirstlane((int)v);
-  };
-  int first = pop();
-  while (first < qe) {
-    const int next = pop();
-    const int last = first + k < qe ? first + k : qe;
-    for (int t = first; t < last; ++t) {
-      const int2 te = B.tasks[t];
-      const int x = __builtin_amdgcn_readfirstlane(te.x);
-      const int y = __builtin_amdgcn_readfirstlane(te.y);
-      const i32x4* src = reinterpret_cast<const i32x4*>(B.plans + x);
-      i32x4* dst = reinterpret_cast<i32x4*>(plan);
-      for (int i = lane; i < (int)(sizeof(DevPlan) / 16); i += 64) dst[i] = src[i];
-      group_sync(true);
-      wg_run<T, C, NS, U, KD, false, true, PF>(*plan, reinterpret_cast<const typename T::Raw*>(B.ins[x]),
-                                               B.outs[x], B.wss[x], (uint32_t)y, scratch);
-      group_sync(true);  // the plan slice is rewritten by the next task
-    }
-    first = next;
-  }
-}
-
-// Kernel families.  Every nest of one persistent launch belongs to one family.
-enum Family : int32_t {
-  FAM_F32_4 = 0, FAM_F32_8, FAM_BF16_4, FAM_BF16_8, FAM_I32_FLAT, FAM_I32_SEG, FAM_I32_DEEP, FAM_COUNT
-};
-__host__ __device__ inline int family_of(const DevPlan& P) {
-  if (P.dtype == HP_F32) return P.depth <= 4 ? FAM_F32_4 : FAM_F32_8;
-  if (P.dtype == HP_BF16) return P.depth <= 4 ? FAM_BF16_4 : FAM_BF16_8;
-  if (P.depth <= 4 && P.nseg <= 1) return FAM_I32_FLAT;
-  if (P.depth <= 4 && P.nseg <= 3) return FAM_I32_SEG;
-  return FAM_I32_DEEP;
-}
-
-// Launch a persistent batch of one family / chunk on `grid` workgroups of nw waves.
-hp_status launch_batch(int family, int chunk, const BatchArgs& B, int grid, int nw, size_t lds, hipStream_t st);
-// Fold the grid-split outputs: n fold tasks over a pointer table of nests.
-hp_status launch_fold(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
-                      unsigned char* const* wss, hipStream_t st);
-// The same for a single plan.
-hp_status launch_fold_one(const DevPlan* plan, const FoldTask* tasks, int n, void* out, const unsigned char* ws,
-                          hipStream_t st);
-// Clear n counters (a kernel, so that it can sit in a captured graph).
-hp_status launch_clear(unsigned int* ctr, int n, hipStream_t st);
-// Deal n tasks, given largest first, round-robin into the queues that a grid of
-// `grid` workgroups serves; writes them queue by queue to `out` and fills B->qbeg
-// and B->per_pop.
-void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B);
-// Counter words one batch launch uses (cleared before each launch).
-constexpr int kCtrWords = kQueues * kCtrStride;
-// Resident workgroups per CU for that kernel.
-int batch_occupancy(int family, int chunk, int nw, size_t lds);
 
 // Launchers, one per input type (each in its own translation unit).  P is the host
 // copy (launch geometry), dP the same plan in device memory (read by the kernel).

@@ -27,9 +27,9 @@ hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, 
   const dim3 grid((unsigned int)P.grid), block((unsigned int)(P.nw * kWave));
   const uint16_t* x = reinterpret_cast<const uint16_t*>(in);
   unsigned char* w = reinterpret_cast<unsigned char*>(ws);
-  if (P.depth <= 4 && P.nid <= 1 && P.nw <= 8 && P.chunk == 8 && !(P.flags & HP_FLAG_GENERIC)) {
+  if (P.kernel == HP_KERNEL_LEAN) {
     hipLaunchKernelGGL(k_nest_bf16_lean<8>, grid, block, lds, st, dP, x, out, w);
-  } else if (P.depth <= 4) {
+  } else if (P.kernel == HP_KERNEL_GENERIC4) {
     if (P.chunk == 8) hipLaunchKernelGGL((k_nest_bf16<8, 4>), grid, block, lds, st, dP, x, out, w);
     else hipLaunchKernelGGL((k_nest_bf16<1, 4>), grid, block, lds, st, dP, x, out, w);
   } else {

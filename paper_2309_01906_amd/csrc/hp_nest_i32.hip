@@ -27,8 +27,8 @@ hp_status launch_nest_i32_deep(const DevPlan& P, const DevPlan* dP, const void* 
 
 // one segment and depth <= 4; two or three segments and depth <= 4; anything else
 hp_status launch_nest_i32(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {
-  if (P.depth <= 4 && P.nseg <= 1) return launch_nest_i32_flat(P, dP, in, out, ws, lds, st);
-  if (P.depth <= 4 && P.nseg <= 3) return launch_nest_i32_seg(P, dP, in, out, ws, lds, st);
+  if (P.kernel == HP_KERNEL_INT_FLAT) return launch_nest_i32_flat(P, dP, in, out, ws, lds, st);
+  if (P.kernel == HP_KERNEL_INT_SEG) return launch_nest_i32_seg(P, dP, in, out, ws, lds, st);
   return launch_nest_i32_deep(P, dP, in, out, ws, lds, st);
 }
 

@@ -450,6 +450,16 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
       if (dp.lv[l].op == HP_OP_ARGMIN || dp.lv[l].op == HP_OP_ARGMAX) { dp.out_kind = OUT_I32; break; }
     }
   }
+  // ---- kernel variant
+  if (is_float) {
+    const int vec = n->dtype == HP_BF16 ? 8 : 4;
+    if (d <= 4 && dp.nid <= 1 && dp.nw <= 8 && dp.chunk == vec && !(flags & HP_FLAG_GENERIC)) dp.kernel = HP_KERNEL_LEAN;
+    else dp.kernel = d <= 4 ? HP_KERNEL_GENERIC4 : HP_KERNEL_GENERIC8;
+  } else {
+    if (d <= 4 && dp.nseg <= 1) dp.kernel = HP_KERNEL_INT_FLAT;
+    else if (d <= 4 && dp.nseg <= 3) dp.kernel = HP_KERNEL_INT_SEG;
+    else dp.kernel = HP_KERNEL_INT_DEEP;
+  }
   // ---- info
   hp_plan_info& I = out->info;
   memset(&I, 0, sizeof I);
@@ -478,6 +488,7 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     I.strips[l] = dp.lv[l].strips;
   }
   I.nseg = dp.nseg;
+  I.kernel = dp.kernel;
   out->dp = dp;
   return HP_OK;
 }

@@ -6,7 +6,7 @@
 
 #include "hp_internal.h"
 
-#include "hp_nest.h"
+#include "hp_fold.h"
 
 struct hp_plan_s {
   hp::DevPlan dp;        // host copy: launch geometry

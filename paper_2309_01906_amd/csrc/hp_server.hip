@@ -25,7 +25,8 @@
 #include <vector>
 
 #include "hp_internal.h"
-#include "hp_nest.h"
+#include "hp_batch_dev.h"
+#include "hp_fold.h"
 #include "hp_tune.h"
 
 namespace {

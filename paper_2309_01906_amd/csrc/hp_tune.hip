@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "hp_internal.h"
-#include "hp_nest.h"
+#include "hp_batch_dev.h"
 #include "hp_tune.h"
 
 struct hp_batch_s;
