@@ -101,7 +101,7 @@ typedef struct hp_level_map {
 #define HP_FLAG_OUT_F32 0x1u   /* float sums stored as fp32 (default fp64) */
 #define HP_FLAG_SCALAR 0x2u    /* one element per load on the innermost level */
 #define HP_FLAG_NO_XCD 0x4u    /* no XCD-contiguous workgroup renumbering */
-#define HP_FLAG_TEMPORAL 0x8u  /* plain (cached) loads instead of nontemporal ones */
+/* 0x8 is reserved.  Inputs are streamed once, so every load is nontemporal. */
 #define HP_FLAG_GENERIC 0x10u  /* always use the general kernel (no lean streaming variant) */
 
 /* What the planner decided; filled by hp_plan_inspect / hp_plan_info. */
@@ -186,7 +186,7 @@ typedef struct hp_batch_s* hp_batch_t;
 /* Plan n nests (each validated as by hp_plan_inspect; batched plans use 4 waves
  * per workgroup) and allocate the batch's device tables, task lists, counters and
  * grid-combine workspaces.  flags: HP_BATCH_GRAPH, HP_BATCH_NO_TUNE,
- * HP_FLAG_OUT_F32, HP_FLAG_TEMPORAL.  HP_EINVAL / HP_EUNSUPPORTED name the first
+ * HP_FLAG_OUT_F32.  HP_EINVAL / HP_EUNSUPPORTED name the first
  * bad nest; HP_ENOMEM if device memory runs out. */
 hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t flags, hp_batch_t* out);
 
@@ -260,7 +260,7 @@ typedef struct hp_server_cfg {
   int32_t max_batch;              /* requests per batch */
   int32_t window_us;              /* how long a partial batch may wait while the device is busy */
   int32_t queue_cap;              /* pending requests before hp_submit returns HP_EAGAIN */
-  uint32_t flags;                 /* HP_FLAG_OUT_F32, HP_FLAG_TEMPORAL, HP_SERVER_FAKE_DEVICE */
+  uint32_t flags;                 /* HP_FLAG_OUT_F32, HP_SERVER_FAKE_DEVICE */
   int32_t fail_every_nth_batch;   /* test hook: every n-th batch fails without running (0: never) */
 } hp_server_cfg;
 

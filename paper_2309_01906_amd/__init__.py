@@ -23,7 +23,7 @@ NONE, SUM, MIN, MAX, ARGMIN, ARGMAX = 0, 1, 2, 3, 4, 5
 I32, F32, BF16, I64, F64 = 0, 1, 2, 3, 4
 SCOPE = {"G": 1, "W": 2, "V": 4, "L": 8}
 AXIS = {"G": 0, "W": 1, "V": 2}
-FLAG_OUT_F32, FLAG_SCALAR, FLAG_NO_XCD, FLAG_TEMPORAL, FLAG_GENERIC = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_OUT_F32, FLAG_SCALAR, FLAG_NO_XCD, FLAG_GENERIC = 0x1, 0x2, 0x4, 0x10
 OP_NAMES = {"NONE": NONE, "SUM": SUM, "MIN": MIN, "MAX": MAX, "ARGMIN": ARGMIN, "ARGMAX": ARGMAX}
 STATUS = ["HP_OK", "HP_EINVAL", "HP_EUNSUPPORTED", "HP_ENOMEM", "HP_EDEVICE", "HP_EAGAIN",
           "HP_ETOOBIG", "HP_ENOTREADY", "HP_ECANCELED", "HP_ESTATE"]

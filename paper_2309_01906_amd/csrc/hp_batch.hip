@@ -185,10 +185,10 @@ extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t fla
   using namespace hp;
   if (!out || !nests || n < 1) return fail(HP_EINVAL, "null argument or empty batch");
   *out = nullptr;
-  if (flags & ~(uint32_t)(HP_BATCH_GRAPH | HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL | HP_BATCH_NO_TUNE))
+  if (flags & ~(uint32_t)(HP_BATCH_GRAPH | HP_FLAG_OUT_F32 | HP_BATCH_NO_TUNE))
     return fail(HP_EINVAL, "unknown batch flag bits 0x%x", flags);
   std::vector<Lowered> plans((size_t)n);
-  const uint32_t pflags = flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL);
+  const uint32_t pflags = flags & HP_FLAG_OUT_F32;
   for (int64_t i = 0; i < n; ++i) {
     hp_status s = plan_for_batch(&nests[i], pflags, !(flags & HP_BATCH_NO_TUNE), kBatchWaves, &plans[(size_t)i]);
     if (s != HP_OK) {
@@ -203,7 +203,7 @@ extern "C" hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t fla
 extern "C" hp_status hp_batch_plan_inspect(const hp_nest* nests, int64_t n, uint32_t flags, hp_plan_info* infos) {
   using namespace hp;
   if (!nests || !infos || n < 1) return fail(HP_EINVAL, "null argument or empty batch");
-  const uint32_t pflags = flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL);
+  const uint32_t pflags = flags & HP_FLAG_OUT_F32;
   for (int64_t i = 0; i < n; ++i) {
     Lowered L;
     hp_status s = plan_for_batch(&nests[i], pflags, !(flags & HP_BATCH_NO_TUNE), kBatchWaves, &L);

@@ -75,6 +75,8 @@ struct alignas(16) DevPlan {
   uint32_t idle_vmask, idle_wmask;  // lane / wave bits assigned to no level
   int32_t lds_slot_lanes;           // 64 if a segment keeps per-lane LDS slots, else 1
   int32_t gq;                       // innermost segment spanning workgroups (0 if none)
+  int32_t vlane32;                  // the lanes of a wave lie within 2^31 bytes of lane 0
+  int32_t pad3;
   // innermost segment, walked as one batched stream: its levels with more than one
   // strip, outer to inner ("inner dims")
   int32_t a;                        // first level of the innermost segment

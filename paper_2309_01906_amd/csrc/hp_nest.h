@@ -205,11 +205,13 @@ struct Chunk<uint16_t, 1> { using V = unsigned short; };
 // Inputs always live in global memory: say so, so that pointers read from tables
 // (batches) still give global loads rather than flat ones (flat loads also count
 // on the LDS counter and would be waited for together with LDS reads).
+// The data is read once: nontemporal loads (the cache policy must be a
+// compile-time property of the load; a runtime choice between two load forms gets
+// merged into a plain load).
 template <class V>
-__device__ __forceinline__ V load_chunk(const void* p, bool nt) {
+__device__ __forceinline__ V load_chunk(const void* p) {
   typedef const __attribute__((address_space(1))) V GV;
-  GV* q = (GV*)(p);
-  return nt ? __builtin_nontemporal_load(q) : *q;
+  return __builtin_nontemporal_load((GV*)(p));
 }
 
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
@@ -300,14 +302,19 @@ struct Thread {
 // more than one strip (1, 2, or any up to KD).  With CHECK, lanes whose chunk is
 // masked out load element 0 instead (always in bounds) and fold the identity, so
 // the loads are never predicated and stay in flight together.
-template <class T, int C, int OP, int U, int ND, int KD, bool CHECK>
+__device__ __forceinline__ long long readfirstlane64(long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(unsigned long long)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+template <class T, int C, int OP, int U, int ND, int KD, bool CHECK, bool FAST = false>
 __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                                   long long base, bool valid, const Thread<KD>& th) {
   using Acc = typename T::Acc;
   using V = typename Chunk<typename T::Raw, C>::V;
   using Raw = typename T::Raw;
   constexpr bool kArg = (OP == HP_OP_ARGMIN || OP == HP_OP_ARGMAX);
-  const bool nt = !(P.flags & HP_FLAG_TEMPORAL);
   const int nid = P.nid;
   Acc a = T::identity(OP);
   long long t_first = 0, span_last = 0;
@@ -322,7 +329,38 @@ __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typena
   }
   const Raw* __restrict__ row = in + base;
   const long long F = P.inner_iters;
-  if constexpr (ND == 1) {
+  if constexpr (ND == 1 && FAST && !CHECK) {
+    // Lean streaming (no masking; the plan guarantees vlane32): the wave's lowest
+    // address lane 0's is kept in scalar registers and each lane adds a 32-bit byte
+    // offset, so a load costs one VGPR of address.  Loads are software-pipelined:
+    // batch k+1 is issued before batch k is folded, so each wave keeps loads in
+    // flight while it computes.
+    const long long ss = nid > 0 ? P.id_sstride[0] : 0;
+    const long long ub = readfirstlane64(base);
+    const uint32_t lo = (uint32_t)((base - ub) * (long long)sizeof(Raw));
+    const char* pu = reinterpret_cast<const char*>(in + ub);
+    const long long ssb = ss * (long long)sizeof(Raw);
+    auto ld = [&](long long f) -> V { return load_chunk<V>((pu + f * ssb) + lo); };
+    const long long Ffull = F - F % U;
+    long long f0 = 0;
+    if (Ffull > 0) {
+      V x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ld(u);
+      for (f0 = U; f0 < Ffull; f0 += U) {
+        V y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) y[u] = ld(f0 + u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) AddChunk<T, C, OP>::run(a, x[u], t_first + (f0 - U + u) * span_last, true);
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = y[u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) AddChunk<T, C, OP>::run(a, x[u], t_first + (f0 - U + u) * span_last, true);
+    }
+    for (; f0 < F; ++f0) AddChunk<T, C, OP>::run(a, ld(f0), t_first + f0 * span_last, true);
+  } else if constexpr (ND == 1) {
     // one strided dimension (or none): chunk f sits at f * sstride.  Full batches
     // are straight-line code (U loads, then U folds); the tail goes one by one.
     const long long ss = nid > 0 ? P.id_sstride[0] : 0;
@@ -338,7 +376,7 @@ __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typena
         const long long f = f0 + u;
         ok[u] = true;
         if constexpr (CHECK) ok[u] = valid && (!rag || f < lim);
-        x[u] = load_chunk<V>(ok[u] ? row + f * ss : in, nt);
+        x[u] = load_chunk<V>(ok[u] ? row + f * ss : in);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) AddChunk<T, C, OP>::run(a, x[u], t_first + (f0 + u) * span_last, ok[u]);
@@ -346,7 +384,7 @@ __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typena
     for (; f0 < F; ++f0) {
       bool ok = true;
       if constexpr (CHECK) ok = valid && (!rag || f0 < lim);
-      const V x = load_chunk<V>(ok ? row + f0 * ss : in, nt);
+      const V x = load_chunk<V>(ok ? row + f0 * ss : in);
       AddChunk<T, C, OP>::run(a, x, t_first + f0 * span_last, ok);
     }
   } else if constexpr (ND == 2) {
@@ -366,7 +404,7 @@ __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typena
         if constexpr (CHECK) ok[u] = valid && (!rag0 || s0 < lim0) && (!rag1 || s1 < lim1);
         sl[u] = s1;
         if (u < nu) {
-          x[u] = load_chunk<V>(ok[u] ? row + soff : in, nt);
+          x[u] = load_chunk<V>(ok[u] ? row + soff : in);
           soff += ss1;
           if (++s1 == S1) {
             s1 = 0;
@@ -401,7 +439,7 @@ __device__ __forceinline__ typename T::Acc stream(const DevPlan& P, const typena
         for (int k = 0; k < KD; ++k)
           if (k == nid - 1) sl[u] = s[k];
         if (u < nu) {
-          x[u] = load_chunk<V>(ok[u] ? row + soff : in, nt);
+          x[u] = load_chunk<V>(ok[u] ? row + soff : in);
           bool carry = true;
 #pragma unroll
           for (int k = KD - 1; k >= 0; --k) {
@@ -437,7 +475,7 @@ __device__ __forceinline__ typename T::Acc stream_any(const DevPlan& P, const ty
   const bool check = rag || __builtin_amdgcn_ballot_w64(!valid) != 0;
   if (LEAN || P.nid <= 1) {  // lean kernels are only launched for plans with nid <= 1
     if (check) return stream<T, C, OP, U, 1, KD, true>(P, in, base, valid, th);
-    return stream<T, C, OP, U, 1, KD, false>(P, in, base, valid, th);
+    return stream<T, C, OP, U, 1, KD, false, LEAN>(P, in, base, valid, th);
   }
   if (P.nid == 2) {
     if (check) return stream<T, C, OP, U, 2, KD, true>(P, in, base, valid, th);
@@ -614,8 +652,7 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
         constexpr int OPI = decltype(opc)::value;
         constexpr int UO = U >= 8 ? U / 2 : U;
         using V = typename Chunk<typename T::Raw, C>::V;
-        const bool nt = !(P.flags & HP_FLAG_TEMPORAL);
-        long long t_first = 0;
+              long long t_first = 0;
 #pragma unroll
         for (int m = 0; m < KD; ++m)
           if (m == P.depth - 1) t_first = th.targ[m];
@@ -632,7 +669,7 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
             ok[u] = false;
             if (u < nu) {
               ok[u] = outer_valid();
-              x[u] = load_chunk<V>(ok[u] ? in + base + soff : in, nt);
+              x[u] = load_chunk<V>(ok[u] ? in + base + soff : in);
               advance();
             }
           }

@@ -20,7 +20,7 @@ k_nest_bf16_lean(const DevPlan* __restrict__ Pd, const uint16_t* __restrict__ in
                unsigned char* __restrict__ ws) {
   extern __shared__ __align__(16) char lds[];
   const DevPlan& P = *Pd;
-  wg_run<FloatT<uint16_t>, C, 1, 8, 4, true>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+  wg_run<FloatT<uint16_t>, C, 1, 4, 4, true>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
 }
 
 hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {

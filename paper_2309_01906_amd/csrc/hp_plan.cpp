@@ -128,7 +128,7 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
 
 hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw) {
   if (!n || !out) return fail(HP_EINVAL, "null argument");
-  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_TEMPORAL | HP_FLAG_GENERIC))
+  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_GENERIC))
     return fail(HP_EINVAL, "unknown flag bits 0x%x", flags);
   const int d = n->depth;
   if (d < 1 || d > kMaxDepth) return fail(HP_EINVAL, "depth %d outside [1, %d]", d, kMaxDepth);
@@ -450,10 +450,18 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
       if (dp.lv[l].op == HP_OP_ARGMIN || dp.lv[l].op == HP_OP_ARGMAX) { dp.out_kind = OUT_I32; break; }
     }
   }
+  // ---- lane spread of a wave: lane 0 has every V digit at 0, so it holds the
+  // wave's lowest address and the others lie at most this far above it
+  {
+    int64_t vspan = 0;
+    for (int l = 0; l < d; ++l) vspan += (int64_t)(dp.lv[l].vf - 1) * dp.lv[l].chunk * dp.lv[l].stride;
+    dp.vlane32 = vspan * elem_bytes(n->dtype) < ((int64_t)1 << 31) ? 1 : 0;
+  }
   // ---- kernel variant
   if (is_float) {
     const int vec = n->dtype == HP_BF16 ? 8 : 4;
-    if (d <= 4 && dp.nid <= 1 && dp.nw <= 8 && dp.chunk == vec && !(flags & HP_FLAG_GENERIC)) dp.kernel = HP_KERNEL_LEAN;
+    if (d <= 4 && dp.nid <= 1 && dp.nw <= 8 && dp.chunk == vec && dp.vlane32 && !(flags & HP_FLAG_GENERIC))
+      dp.kernel = HP_KERNEL_LEAN;
     else dp.kernel = d <= 4 ? HP_KERNEL_GENERIC4 : HP_KERNEL_GENERIC8;
   } else {
     if (d <= 4 && dp.nseg <= 1) dp.kernel = HP_KERNEL_INT_FLAT;

@@ -380,7 +380,7 @@ extern "C" hp_status hp_submit(hp_server_t S, const hp_nest* nest, const void* d
   if (S->stop.load()) return fail(HP_ESTATE, "server is shutting down");
   Request r;
   memset(&r.info, 0, sizeof r.info);
-  hp_status s = plan_for_batch(nest, (uint32_t)(S->cfg.flags & (HP_FLAG_OUT_F32 | HP_FLAG_TEMPORAL)), true,
+  hp_status s = plan_for_batch(nest, (uint32_t)(S->cfg.flags & HP_FLAG_OUT_F32), true,
                                kBatchWaves, &r.L);
   if (s != HP_OK) return s;
   const uintptr_t al = (r.L.info.out_dtype == HP_I64 || r.L.info.out_dtype == HP_F64) ? 7u : 3u;

@@ -203,10 +203,10 @@ def test_argmin_ties_first_occurrence():
         assert_match(got, x, ext, ops, what=f"ties {ext}")
 
 
-def test_flags_scalar_out_f32_temporal_noxcd():
+def test_flags_scalar_out_f32_noxcd_generic():
     import paper_2309_01906_amd as hp
     x = workloads.normal_f32(73, (256, 4096))
-    for fl in [hp.FLAG_SCALAR, hp.FLAG_OUT_F32, hp.FLAG_TEMPORAL, hp.FLAG_NO_XCD]:
+    for fl in [hp.FLAG_SCALAR, hp.FLAG_OUT_F32, hp.FLAG_NO_XCD, hp.FLAG_GENERIC]:
         got, info = gpu_reduce(x, x.shape, ("NONE", "SUM"), flags=fl)
         if fl == hp.FLAG_OUT_F32:
             assert got.dtype == np.float32
