@@ -26,47 +26,59 @@ struct BatchArgs {
 };
 
 // Wave tasks: every wavefront of the workgroup is an independent worker running
-// one-wave plans (no workgroup barrier), with its own slice of LDS.  The task's
-// plan is first copied into that slice, so the kernel reads it from LDS instead of
-// with vector loads that would queue behind the data stream.  The next task index
-// is taken before the current task runs, so the atomic's latency overlaps it.
-constexpr int kPlanLdsBytes = (int)((sizeof(DevPlan) + 255) / 256 * 256);
-constexpr int kWaveLdsBytes = kPlanLdsBytes + 256;
-static_assert(sizeof(DevPlan) % 16 == 0, "plans are copied in 16-byte words");
+// one-wave plans (no workgroup barrier), with its own small slice of LDS.  The next
+// task index is taken before the current task runs, so the atomic's latency
+// overlaps it.
+constexpr int kWaveLdsBytes = 256;
 
 template <class T, int C, int NS, int U, int KD, bool PF = true>
 __device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
   const int w = (int)(threadIdx.x >> 6);
   const int lane = (int)(threadIdx.x & 63);
-  char* mine = lds + w * kWaveLdsBytes;
-  DevPlan* plan = reinterpret_cast<DevPlan*>(mine);
-  char* scratch = mine + kPlanLdsBytes;
+  char* scratch = lds + w * kWaveLdsBytes;
   const int q = (int)(blockIdx.x % kQueues);
   const int qb = B.qbeg[q], qe = B.qbeg[q + 1];
   const int k = B.per_pop;
+  // Workers of queue q: the waves of workgroups q, q + 8, ...  Worker r starts on
+  // tasks [qb + r k, qb + r k + k) without touching the counter; the counter hands
+  // out what follows the static part.
+  const int nblk = ((int)gridDim.x - q + kQueues - 1) / kQueues;
+  const int nwq = nblk * (int)(blockDim.x >> 6);
+  const int r = (int)(blockIdx.x / kQueues) * (int)(blockDim.x >> 6) + w;
+  const long long dyn0 = (long long)qb + (long long)nwq * k;
   unsigned int* ctr = B.ctr + q * kCtrStride;
+  // The atomic's result is only needed after the current task, so the wave does not
+  // wait for it here.
   auto pop = [&]() -> int {
     unsigned int v = 0;
     if (lane == 0) v = __hip_atomic_fetch_add(ctr, (unsigned int)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return qb + __builtin_amdgcn_readfirstlane((int)v);
+    const long long t = dyn0 + (unsigned int)__builtin_amdgcn_readfirstlane((int)v);
+    return t < qe ? (int)t : qe;
   };
-  int first = pop();
-  while (first < qe) {
-    const int next = pop();
-    const int last = first + k < qe ? first + k : qe;
-    for (int t = first; t < last; ++t) {
-      const int2 te = B.tasks[t];
-      const int x = __builtin_amdgcn_readfirstlane(te.x);
-      const int y = __builtin_amdgcn_readfirstlane(te.y);
-      const i32x4* src = reinterpret_cast<const i32x4*>(B.plans + x);
-      i32x4* dst = reinterpret_cast<i32x4*>(plan);
-      for (int i = lane; i < (int)(sizeof(DevPlan) / 16); i += 64) dst[i] = src[i];
-      group_sync(true);
-      wg_run<T, C, NS, U, KD, false, true, PF>(*plan, reinterpret_cast<const typename T::Raw*>(B.ins[x]),
-                                               B.outs[x], B.wss[x], (uint32_t)y, scratch);
-      group_sync(true);  // the plan slice is rewritten by the next task
+  // Plans and task entries do not change while the kernel runs: read them through
+  // the constant address space, so they arrive in scalar registers by scalar loads
+  // and never queue behind the data stream's vector loads.
+  typedef const __attribute__((address_space(4))) DevPlan CPlan;
+  typedef const __attribute__((address_space(4))) int CInt;
+  CPlan* plans = (CPlan*)(B.plans);
+  CInt* tasks = (CInt*)(B.tasks);  // (nest, workgroup) pairs
+  long long t0 = (long long)qb + (long long)r * k;
+  int t = t0 < qe ? (int)t0 : qe;
+  int t_end = t0 + k < qe ? (int)(t0 + k) : qe;
+  while (t < t_end) {
+    const int x = __builtin_amdgcn_readfirstlane(tasks[2 * (long long)t]);
+    const int y = __builtin_amdgcn_readfirstlane(tasks[2 * (long long)t + 1]);
+    int u = t + 1, u_end = t_end;
+    if (u == t_end) {
+      u = pop();
+      u_end = u + k < qe ? u + k : qe;
     }
-    first = next;
+    wg_run<T, C, NS, U, KD, false, true, PF>(*(const DevPlan*)(plans + x),
+                                             reinterpret_cast<const typename T::Raw*>(B.ins[x]), B.outs[x],
+                                             B.wss[x], (uint32_t)y, scratch);
+    group_sync(true);  // the scratch slice is reused by the next task
+    t = u;
+    t_end = u_end;
   }
 }
 

@@ -3,24 +3,24 @@
 
 namespace hp {
 
-__global__ void __launch_bounds__(1024) k_batch_f32_0(const BatchArgs B) {
+__global__ void __launch_bounds__(256) k_batch_f32_0(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<FloatT<float>, 4, 1, 8, 4>(B, lds);
+  batch_run_waves<FloatT<float>, 4, 1, 4, 4>(B, lds);
 }
 
-__global__ void __launch_bounds__(1024) k_batch_f32_1(const BatchArgs B) {
+__global__ void __launch_bounds__(256) k_batch_f32_1(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<FloatT<float>, 1, 1, 16, 4>(B, lds);
+  batch_run_waves<FloatT<float>, 1, 1, 4, 4>(B, lds);
 }
 
-__global__ void __launch_bounds__(1024) k_batch_f32_2(const BatchArgs B) {
+__global__ void __launch_bounds__(256) k_batch_f32_2(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<FloatT<float>, 4, 1, 8, kMaxDepth>(B, lds);
+  batch_run_waves<FloatT<float>, 4, 1, 4, kMaxDepth>(B, lds);
 }
 
-__global__ void __launch_bounds__(1024) k_batch_f32_3(const BatchArgs B) {
+__global__ void __launch_bounds__(256) k_batch_f32_3(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<FloatT<float>, 1, 1, 16, kMaxDepth>(B, lds);
+  batch_run_waves<FloatT<float>, 1, 1, 4, kMaxDepth>(B, lds);
 }
 
 static hp_status launch_check() {

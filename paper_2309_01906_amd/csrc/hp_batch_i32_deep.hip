@@ -3,12 +3,12 @@
 
 namespace hp {
 
-__global__ void __launch_bounds__(1024) k_batch_i32_deep_0(const BatchArgs B) {
+__global__ void __launch_bounds__(256) k_batch_i32_deep_0(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
   batch_run_waves<IntT, 4, kMaxDepth, 4, kMaxDepth, false>(B, lds);
 }
 
-__global__ void __launch_bounds__(1024) k_batch_i32_deep_1(const BatchArgs B) {
+__global__ void __launch_bounds__(256) k_batch_i32_deep_1(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
   batch_run_waves<IntT, 1, kMaxDepth, 4, kMaxDepth, false>(B, lds);
 }

@@ -473,9 +473,9 @@ __device__ __forceinline__ typename T::Acc stream_any(const DevPlan& P, const ty
   for (int k = 0; k < KD; ++k)
     if (k < P.nid && P.id_ragged[k]) rag = true;
   const bool check = rag || __builtin_amdgcn_ballot_w64(!valid) != 0;
-  if (LEAN || P.nid <= 1) {  // lean kernels are only launched for plans with nid <= 1
-    if (check) return stream<T, C, OP, U, 1, KD, true>(P, in, base, valid, th);
-    return stream<T, C, OP, U, 1, KD, false, LEAN>(P, in, base, valid, th);
+  if (LEAN || P.nid <= 1) {  // lean kernels are only launched for plans with nid <= 1 and vlane32
+    if (check || !(LEAN || P.vlane32)) return stream<T, C, OP, U, 1, KD, true>(P, in, base, valid, th);
+    return stream<T, C, OP, (U < 4 ? U : 4), 1, KD, false, true>(P, in, base, valid, th);
   }
   if (P.nid == 2) {
     if (check) return stream<T, C, OP, U, 2, KD, true>(P, in, base, valid, th);
