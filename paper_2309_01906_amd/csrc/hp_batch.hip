@@ -97,6 +97,26 @@ hp_status launch_fold_one(const DevPlan* plan, const FoldTask* tasks, int n, voi
   return HP_OK;
 }
 
+hp_status warm_batch_kernels(hipStream_t st) {
+  BatchArgs A;
+  memset(&A, 0, sizeof A);  // empty queues: every worker exits at once, nothing is read
+  A.per_pop = 1;
+  const size_t lds = (size_t)kBatchGroupWaves * kWaveLdsBytes;
+  const int fams[][2] = {{FAM_F32_4, 4}, {FAM_F32_4, 1}, {FAM_F32_8, 4}, {FAM_F32_8, 1},
+                         {FAM_BF16_4, 8}, {FAM_BF16_4, 1}, {FAM_BF16_8, 8}, {FAM_BF16_8, 1},
+                         {FAM_I32_FLAT, 4}, {FAM_I32_FLAT, 1}, {FAM_I32_SEG, 4}, {FAM_I32_SEG, 1},
+                         {FAM_I32_DEEP, 4}, {FAM_I32_DEEP, 1}};
+  for (const auto& f : fams) {
+    hp_status s = launch_batch(f[0], f[1], A, 1, kBatchGroupWaves, lds, st);
+    if (s != HP_OK) return s;
+  }
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, (const DevPlan*)nullptr, (const FoldTask*)nullptr, 0,
+                     (void* const*)nullptr, (unsigned char* const*)nullptr);
+  hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, (unsigned int*)nullptr, 0);
+  if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "warm-up launch failed");
+  return HP_OK;
+}
+
 void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B) {
   const int nq = grid < kQueues ? (grid < 1 ? 1 : grid) : kQueues;
   int pos = 0;

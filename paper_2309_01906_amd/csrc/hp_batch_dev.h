@@ -96,6 +96,9 @@ __host__ __device__ inline int family_of(const DevPlan& P) {
 
 // Launch a persistent batch of one family / chunk on `grid` workgroups of nw waves.
 hp_status launch_batch(int family, int chunk, const BatchArgs& B, int grid, int nw, size_t lds, hipStream_t st);
+// Launch every persistent kernel once with no tasks (and the counter and fold
+// kernels), so that code objects are loaded before the first real batch.
+hp_status warm_batch_kernels(hipStream_t st);
 // Clear n counters (a kernel, so that it can sit in a captured graph).
 hp_status launch_clear(unsigned int* ctr, int n, hipStream_t st);
 // Deal n tasks, given largest first, round-robin into the queues that a grid of

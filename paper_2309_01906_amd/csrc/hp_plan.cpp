@@ -63,6 +63,46 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
     }
     return;
   }
+  int64_t block = 1;
+  for (int k = p; k < d; ++k) block *= n->extent[k];
+  const int64_t bytes = block * elem_bytes(n->dtype);
+  // Small blocks and many outputs: one output needs fewer lanes than a wave has, so
+  // the innermost output level also takes the rest of the lanes and the waves, and
+  // strips of it give every workgroup a useful amount of input.
+  if (p >= 1 && bytes < (16 << 10) && n->extent[p - 1] > 1) {
+    uint64_t pw = 1;
+    for (int k = d - 1; k >= p; --k) pw *= pow2ceil((uint64_t)cdiv(n->extent[k], k == d - 1 ? chunk_last : 1));
+    if (pw < (uint64_t)kWave) {
+      int lanes = (int)pw;
+      for (int k = d - 1; k >= p; --k) {
+        uint64_t f = pow2ceil((uint64_t)cdiv(n->extent[k], k == d - 1 ? chunk_last : 1));
+        if (f > (uint64_t)lanes || k == p) f = (uint64_t)lanes;
+        m->scopes[k] = HP_SCOPE_V;
+        m->units[k][HP_AXIS_V] = (uint32_t)f;
+        lanes /= (int)f;
+      }
+      const int64_t eo = n->extent[p - 1];
+      const int64_t parts = kWave / (int64_t)pw;
+      int64_t nw = force_nw > 0 ? force_nw : (int64_t)pow2ceil((uint64_t)cdiv(eo, parts));
+      if (nw > 4) nw = 4;
+      const int64_t per_pass = parts * nw;
+      // outputs per workgroup: about 32 KiB of input, but at least 1024 workgroups
+      // for a single nest (a batch fills the chip with other nests' tasks)
+      int64_t opt = ((32 << 10) / (bytes > 0 ? bytes : 1)) / per_pass * per_pass;
+      if (force_nw == 0) {
+        int64_t n_out = 1;
+        for (int k = 0; k < p; ++k) n_out *= n->extent[k];
+        const int64_t spread = cdiv(cdiv(n_out, 1024), per_pass) * per_pass;
+        if (opt > spread) opt = spread;
+      }
+      if (opt < per_pass) opt = per_pass;
+      m->scopes[p - 1] = HP_SCOPE_G | HP_SCOPE_W | (parts > 1 ? HP_SCOPE_V : 0u);
+      m->units[p - 1][HP_AXIS_G] = (uint32_t)cdiv(eo, opt);
+      m->units[p - 1][HP_AXIS_W] = (uint32_t)nw;
+      if (parts > 1) m->units[p - 1][HP_AXIS_V] = (uint32_t)parts;
+      return;
+    }
+  }
   // lanes of one wavefront, innermost reducing level first
   int lanes_left = kWave;
   int l = d - 1;
@@ -78,9 +118,6 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
     --l;
   }
   if (lanes_left > 1) m->units[first_v][HP_AXIS_V] *= (uint32_t)lanes_left;
-  int64_t block = 1;
-  for (int k = p; k < d; ++k) block *= n->extent[k];
-  const int64_t bytes = block * elem_bytes(n->dtype);
   const uint64_t nw_target = bytes >= (256 << 10) ? 8 : bytes >= (16 << 10) ? 4 : bytes >= (4 << 10) ? 2 : 1;
   // waves of one workgroup: the next level outward, or the outermost lane level
   int w_level;

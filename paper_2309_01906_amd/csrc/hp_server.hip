@@ -360,6 +360,27 @@ extern "C" hp_status hp_server_create(const hp_server_cfg* cfg, hp_server_t* out
       }
     }
   }
+  if (!S->fake) {
+    // load the kernels and learn their occupancy now, not on the first requests
+    const size_t lds = (size_t)kBatchGroupWaves * kWaveLdsBytes;
+    for (int fam = 0; fam < FAM_COUNT; ++fam)
+      for (int chunk : {1, 4, 8}) {
+        const bool ok = chunk == 1 || (chunk == 8) == (fam == FAM_BF16_4 || fam == FAM_BF16_8);
+        if (!ok) continue;
+        int o = batch_occupancy(fam, chunk, kBatchGroupWaves, lds);
+        S->occ[occ_key(fam, chunk)] = o < 1 ? 1 : o;
+      }
+    if (warm_batch_kernels(S->slots[0].st) != HP_OK || hipStreamSynchronize(S->slots[0].st) != hipSuccess) {
+      for (Slot& q : S->slots) {
+        (void)hipStreamDestroy(q.st);
+        (void)hipEventDestroy(q.ev);
+        (void)hipFree(q.d_arena);
+        (void)hipHostFree(q.h_stage);
+      }
+      delete S;
+      return fail(HP_EDEVICE, "kernel warm-up failed");
+    }
+  }
   S->th = std::thread(scheduler, S);
   *out = S;
   return HP_OK;

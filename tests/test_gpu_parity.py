@@ -189,6 +189,32 @@ def test_edge_shapes_float(ext, ops):
     assert_match(got, x, ext, ops, what=f"{ext} {ops}")
 
 
+@pytest.mark.parametrize("ext,ops,lo,hi", [
+    ((20011, 1), ("NONE", "ARGMIN"), -5, 5), ((7001, 3, 5), ("NONE", "SUM", "ARGMIN"), 0, 3),
+    ((6482, 2, 64), ("NONE", "MAX", "MAX"), -(2**31), 2**31 - 1), ((3, 999, 2, 3), ("NONE", "NONE", "MIN", "ARGMAX"), 0, 2),
+    ((100003, 2), ("NONE", "SUM"), -(2**31), 2**31 - 1),
+])
+def test_packed_outputs_int(ext, ops, lo, hi):
+    """Small blocks: the innermost output level shares the wave's lanes with the
+    reduced block (several outputs per wave), with ragged strips and ARG ties."""
+    say("case packed int", ext, ops)
+    x = workloads.uniform_i32(75, ext, lo, hi)
+    got, info = gpu_reduce(x, ext, ops)
+    p = next(i for i, o in enumerate(ops) if o != "NONE")
+    assert "V" in info["map"][p - 1], info["map"]
+    assert_match(got, x, ext, ops, what=f"packed {ext} {ops}")
+
+
+@pytest.mark.parametrize("ext", [(4097, 7), (9999, 3, 3), (50001, 12)])
+def test_packed_outputs_float(ext):
+    say("case packed float", ext)
+    ops = ("NONE",) + ("SUM",) * (len(ext) - 1)
+    x = workloads.normal_f32(76, ext)
+    got, info = gpu_reduce(x, ext, ops)
+    assert "V" in info["map"][0], info["map"]
+    assert_match(got, x, ext, ops, what=f"packed {ext}")
+
+
 def test_int_sum_of_int32_min_needs_64_bits():
     x = np.full((4, 4096), np.iinfo(np.int32).min, np.int32)
     got, _ = gpu_reduce(x, x.shape, ("NONE", "SUM"))
