@@ -22,8 +22,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-NONE, SUM, MIN, MAX, ARGMIN, ARGMAX = 0, 1, 2, 3, 4, 5
-I32, F32, BF16 = 0, 1, 2
+NONE, SUM, MIN, MAX, ARGMIN, ARGMAX, PROD = 0, 1, 2, 3, 4, 5, 6
+I32, F32, BF16, AFFINE, MAT2 = 0, 1, 2, 5, 6
+WIDTH = {AFFINE: 2, MAT2: 4}  # uint64 words per element of the ordered-product types
 OUT_I32, OUT_I64, OUT_F64 = 0, 1, 2
 _OUT_NP = {OUT_I32: np.int32, OUT_I64: np.int64, OUT_F64: np.float64}
 _IN_NP = {I32: np.int32, F32: np.float32, BF16: np.uint16}
@@ -58,6 +59,8 @@ def _load():
         lib.oracle_reduce_range.restype = ctypes.c_int
         lib.oracle_abs_sum_range.argtypes = lib.oracle_reduce_range.argtypes
         lib.oracle_abs_sum_range.restype = ctypes.c_int
+        lib.oracle_prod_range.argtypes = lib.oracle_reduce_range.argtypes
+        lib.oracle_prod_range.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -125,6 +128,29 @@ def abs_sum(x: np.ndarray, extents, ops, dtype, threads: int = 1, o_begin: int =
     d, e, o = _arrays(extents, ops)
     rc = _load().oracle_abs_sum_range(d, e, o, int(dtype), x.ctypes.data, out.ctypes.data,
                                       int(o_begin), int(o_end), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the nest or range")
+    return out
+
+
+def prod(x: np.ndarray, extents, ops, dtype, threads: int = 1, o_begin: int = 0,
+         o_end: int | None = None) -> np.ndarray:
+    """Ordered products (levels PROD, after a NONE prefix) over ``x``: uint64 of
+    shape extents + (width,), width 2 for AFFINE and 4 for MAT2.  Returns the
+    outputs [o_begin, o_end) as uint64 of shape (count, width)."""
+    w = WIDTH[dtype]
+    if x.dtype != np.uint64 or not x.flags.c_contiguous:
+        raise TypeError("input must be C-contiguous uint64")
+    if x.size != int(np.prod(extents, dtype=np.int64)) * w:
+        raise ValueError("input size does not match the extents")
+    p = next((i for i, o in enumerate(ops) if o != NONE), len(ops))
+    total = int(np.prod(extents[:p], dtype=np.int64))
+    if o_end is None:
+        o_end = total
+    out = np.empty((o_end - o_begin, w), np.uint64)
+    d, e, o = _arrays(extents, ops)
+    rc = _load().oracle_prod_range(d, e, o, int(dtype), x.ctypes.data, out.ctypes.data,
+                                   int(o_begin), int(o_end), int(threads))
     if rc != 0:
         raise ValueError("oracle rejected the nest or range")
     return out

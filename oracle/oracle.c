@@ -266,3 +266,124 @@ int oracle_abs_sum_range(int depth, const int64_t* extents, const int* ops, int 
   if (o_begin < 0 || o_end > nout || o_begin > o_end) return -1;
   return run_range(&n, out, o_begin, o_end, threads, 1);
 }
+
+/* ---- ordered products ------------------------------------------------------ */
+
+typedef struct {
+  uint64_t v[4];
+} elem_t; /* affine: v[0] = a, v[1] = b; mat2: row-major m00 m01 m10 m11 */
+
+typedef struct {
+  int d, p, dtype, width; /* width: uint64 words per element */
+  int64_t e[OR_MAX_DEPTH];
+  int64_t stride[OR_MAX_DEPTH];
+  const uint64_t* in;
+} pnest_t;
+
+static elem_t p_identity(int dtype) {
+  elem_t r;
+  memset(&r, 0, sizeof r);
+  r.v[0] = 1;
+  if (dtype == OR_MAT2) r.v[3] = 1;
+  return r;
+}
+
+/* x * y: x first, y second */
+static elem_t p_mul(int dtype, elem_t x, elem_t y) {
+  elem_t r;
+  memset(&r, 0, sizeof r);
+  if (dtype == OR_AFFINE) {
+    r.v[0] = x.v[0] * y.v[0];
+    r.v[1] = y.v[0] * x.v[1] + y.v[1];
+  } else {
+    r.v[0] = x.v[0] * y.v[0] + x.v[1] * y.v[2];
+    r.v[1] = x.v[0] * y.v[1] + x.v[1] * y.v[3];
+    r.v[2] = x.v[2] * y.v[0] + x.v[3] * y.v[2];
+    r.v[3] = x.v[2] * y.v[1] + x.v[3] * y.v[3];
+  }
+  return r;
+}
+
+static elem_t p_load(const pnest_t* n, int64_t off) {
+  elem_t r;
+  int k;
+  memset(&r, 0, sizeof r);
+  for (k = 0; k < n->width; ++k) r.v[k] = n->in[off * n->width + k];
+  return r;
+}
+
+/* R_m at element offset off: children t = 0..e_m-1 multiplied left to right */
+static elem_t p_eval(const pnest_t* n, int m, int64_t off) {
+  elem_t acc = p_identity(n->dtype);
+  int64_t t;
+  if (m == n->d) return p_load(n, off);
+  for (t = 0; t < n->e[m]; ++t) acc = p_mul(n->dtype, acc, p_eval(n, m + 1, off + t * n->stride[m]));
+  return acc;
+}
+
+typedef struct {
+  const pnest_t* n;
+  uint64_t* out;
+  int64_t b, e, base, block;
+} ppart_t;
+
+static void* p_part(void* arg) {
+  const ppart_t* q = (const ppart_t*)arg;
+  int64_t o;
+  int k;
+  for (o = q->b; o < q->e; ++o) {
+    elem_t r = p_eval(q->n, q->n->p, o * q->block);
+    for (k = 0; k < q->n->width; ++k) q->out[(o - q->base) * q->n->width + k] = r.v[k];
+  }
+  return NULL;
+}
+
+int oracle_prod_range(int depth, const int64_t* extents, const int* ops, int dtype, const void* in,
+                      void* out, int64_t o_begin, int64_t o_end, int threads) {
+  pnest_t n;
+  pthread_t th[256];
+  ppart_t parts[256];
+  int64_t nout = 1, block = 1, cnt, per;
+  int m, t, started = 0;
+  if (depth < 1 || depth > OR_MAX_DEPTH || !in || !out) return -1;
+  if (dtype != OR_AFFINE && dtype != OR_MAT2) return -1;
+  n.d = depth;
+  n.dtype = dtype;
+  n.width = dtype == OR_AFFINE ? 2 : 4;
+  n.in = (const uint64_t*)in;
+  n.p = depth;
+  for (m = 0; m < depth; ++m) {
+    if (extents[m] < 1) return -1;
+    if (ops[m] != OR_NONE && ops[m] != OR_PROD) return -1;
+    if (ops[m] == OR_PROD && n.p == depth) n.p = m;
+    if (ops[m] == OR_NONE && n.p != depth) return -1;
+    n.e[m] = extents[m];
+  }
+  n.stride[depth - 1] = 1;
+  for (m = depth - 2; m >= 0; --m) n.stride[m] = n.stride[m + 1] * n.e[m + 1];
+  for (m = 0; m < n.p; ++m) nout *= n.e[m];
+  for (m = n.p; m < depth; ++m) block *= n.e[m];
+  if (o_begin < 0 || o_end > nout || o_begin > o_end) return -1;
+  cnt = o_end - o_begin;
+  if (threads < 1) threads = 1;
+  if (threads > 256) threads = 256;
+  if (cnt < threads) threads = cnt > 0 ? (int)cnt : 1;
+  per = (cnt + threads - 1) / threads;
+  for (t = 0; t < threads; ++t) {
+    parts[t].n = &n;
+    parts[t].out = (uint64_t*)out;
+    parts[t].base = o_begin;
+    parts[t].block = block;
+    parts[t].b = o_begin + per * t;
+    parts[t].e = o_begin + per * (t + 1) > o_end ? o_end : o_begin + per * (t + 1);
+    if (parts[t].b > parts[t].e) parts[t].b = parts[t].e;
+  }
+  for (t = 1; t < threads; ++t) {
+    if (pthread_create(&th[t], NULL, p_part, &parts[t]) != 0) break;
+    started = t;
+  }
+  p_part(&parts[0]);
+  for (t = started + 1; t < threads; ++t) p_part(&parts[t]);
+  for (t = 1; t <= started; ++t) pthread_join(th[t], NULL);
+  return 0;
+}

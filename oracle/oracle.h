@@ -61,6 +61,28 @@ int oracle_reduce(int depth, const int64_t* extents, const int* ops, int dtype,
 int oracle_abs_sum_range(int depth, const int64_t* extents, const int* ops, int dtype,
                          const void* in, double* out, int64_t o_begin, int64_t o_end, int threads);
 
+/* ---- ordered products (associative, not commutative) ----------------------
+ *
+ * The paper notes that OpenMP reductions must be commutative; the recursive
+ * definition above only needs associativity if the siblings are combined in
+ * sibling order.  An ordered product level OR_PROD takes, for t = 0..e_m-1 in
+ * ascending order,
+ *     R_m = R_{m+1}(t=0) * R_{m+1}(t=1) * ... * R_{m+1}(t=e_m-1)
+ * (left to right, never reordered).  Two element types, both with arithmetic
+ * modulo 2^64 (unsigned wrap), so every result is exact:
+ *   OR_AFFINE : an element is (a, b), two uint64, the map x -> a x + b;
+ *               (a1, b1) * (a2, b2) = (a1 a2, a2 b1 + b2), i.e. the first map
+ *               applied first (the step of a linear recurrence x <- a x + b);
+ *               identity (1, 0).
+ *   OR_MAT2   : an element is a 2x2 matrix of uint64, row-major (m00 m01 m10 m11);
+ *               * is the matrix product; identity the unit matrix.
+ * Every reducing level of such a nest is OR_PROD; the output holds one element
+ * (16 or 32 bytes) per output index.  Returns 0, or -1 for an invalid nest. */
+enum { OR_AFFINE = 5, OR_MAT2 = 6 };
+enum { OR_PROD = 6 };
+int oracle_prod_range(int depth, const int64_t* extents, const int* ops, int dtype, const void* in,
+                      void* out, int64_t o_begin, int64_t o_end, int threads);
+
 #ifdef __cplusplus
 }
 #endif

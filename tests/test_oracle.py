@@ -293,3 +293,105 @@ def test_output_range():
     ops = (NONE, SUM, MAX, ARGMIN)
     full = oracle.reduce(a, a.shape, ops, I32)
     np.testing.assert_array_equal(oracle.reduce(a, a.shape, ops, I32, o_begin=3, o_end=6), full[3:6])
+
+
+# ---------------------------------------------------------------------------
+# ordered (non-commutative) products: affine maps and 2x2 matrices modulo 2^64
+
+M64 = (1 << 64) - 1
+PROD, AFFINE, MAT2 = oracle.PROD, oracle.AFFINE, oracle.MAT2
+
+
+def _py_affine_run(elems, x0):
+    """Run the recurrence x <- a x + b over the elements in order (Python ints)."""
+    x = x0
+    for a, b in elems:
+        x = (int(a) * x + int(b)) & M64
+    return x
+
+
+def _py_mat_prod(mats):
+    r = [1, 0, 0, 1]
+    for m in mats:
+        m = [int(v) for v in m]
+        r = [(r[0] * m[0] + r[1] * m[2]) & M64, (r[0] * m[1] + r[1] * m[3]) & M64,
+             (r[2] * m[0] + r[3] * m[2]) & M64, (r[2] * m[1] + r[3] * m[3]) & M64]
+    return r
+
+
+def test_affine_closed_forms():
+    x = np.zeros((3, 70, 2), np.uint64)
+    x[..., 0] = 1
+    x[..., 1] = 1
+    np.testing.assert_array_equal(oracle.prod(x, (3, 70), (NONE, PROD), AFFINE), [[1, 70]] * 3)
+    x[..., 0] = 2
+    x[..., 1] = 0
+    got = oracle.prod(x[:, :63].copy(), (3, 63), (NONE, PROD), AFFINE)
+    np.testing.assert_array_equal(got, [[1 << 63, 0]] * 3)
+    np.testing.assert_array_equal(oracle.prod(x, (3, 70), (NONE, PROD), AFFINE), [[0, 0]] * 3)
+
+
+def test_affine_product_runs_the_recurrence():
+    """(A, B) of the ordered product maps x0 to the recurrence's end value."""
+    x = workloads.monoid_input(101, (4, 97), AFFINE)
+    got = oracle.prod(x, (4, 97), (NONE, PROD), AFFINE)
+    for o in range(4):
+        for x0 in (0, 1, 12345, M64):
+            want = _py_affine_run(x[o], x0)
+            assert (int(got[o, 0]) * x0 + int(got[o, 1])) & M64 == want
+
+
+def test_matrix_closed_forms():
+    # Fibonacci: [[1,1],[1,0]]^n = [[F(n+1), F(n)], [F(n), F(n-1)]]
+    n = 150
+    f = [0, 1]
+    for _ in range(n + 1):
+        f.append(f[-1] + f[-2])
+    x = np.tile(np.array([1, 1, 1, 0], np.uint64), (1, n, 1))
+    got = oracle.prod(x, (1, n), (NONE, PROD), MAT2)[0]
+    assert [int(v) for v in got] == [f[n + 1] & M64, f[n] & M64, f[n] & M64, f[n - 1] & M64]
+    # shear: [[1,1],[0,1]]^n = [[1,n],[0,1]]
+    s = np.tile(np.array([1, 1, 0, 1], np.uint64), (2, 1000, 1))
+    np.testing.assert_array_equal(oracle.prod(s, (2, 1000), (NONE, PROD), MAT2), [[1, 1000, 0, 1]] * 2)
+
+
+def test_matrix_product_is_ordered():
+    """Brute force with Python integers, and the reversed order differs."""
+    x = workloads.monoid_input(102, (5, 33), MAT2)
+    got = oracle.prod(x, (5, 33), (NONE, PROD), MAT2)
+    for o in range(5):
+        assert [int(v) for v in got[o]] == _py_mat_prod(x[o])
+        assert [int(v) for v in got[o]] != _py_mat_prod(x[o][::-1])
+    y = workloads.monoid_input(103, (5, 33), AFFINE)
+    fwd = oracle.prod(y, (5, 33), (NONE, PROD), AFFINE)
+    rev = oracle.prod(y[:, ::-1].copy(), (5, 33), (NONE, PROD), AFFINE)
+    assert np.any(fwd != rev)
+
+
+@pytest.mark.parametrize("kind", [AFFINE, MAT2])
+def test_nested_products_equal_flat_ones(kind):
+    """Associativity: nested PROD levels equal one flat level over the block."""
+    x = workloads.monoid_input(104, (3, 4, 6, 7), kind)
+    flat = oracle.prod(x.reshape(3, 168, -1).copy(), (3, 168), (NONE, PROD), kind)
+    nested = oracle.prod(x, (3, 4, 6, 7), (NONE, PROD, PROD, PROD), kind)
+    np.testing.assert_array_equal(flat, nested)
+    two = oracle.prod(x, (3, 4, 6, 7), (NONE, NONE, PROD, PROD), kind)
+    # out[i] = prod over j of out2[i, j]: the outer level applied to the inner results
+    again = oracle.prod(two.reshape(3, 4, -1).copy(), (3, 4), (NONE, PROD), kind)
+    np.testing.assert_array_equal(again, flat)
+
+
+def test_products_reject_mixed_operators_and_types():
+    x = workloads.monoid_input(105, (2, 3), AFFINE)
+    with pytest.raises(ValueError):
+        oracle.prod(x, (2, 3), (NONE, SUM), AFFINE)
+    with pytest.raises(ValueError):
+        oracle.prod(x, (2, 3), (PROD, NONE), AFFINE)
+
+
+def test_product_threads_and_ranges():
+    x = workloads.monoid_input(106, (50, 20), MAT2)
+    r1 = oracle.prod(x, (50, 20), (NONE, PROD), MAT2, threads=1)
+    r5 = oracle.prod(x, (50, 20), (NONE, PROD), MAT2, threads=5)
+    np.testing.assert_array_equal(r1, r5)
+    np.testing.assert_array_equal(oracle.prod(x, (50, 20), (NONE, PROD), MAT2, o_begin=7, o_end=19), r1[7:19])

@@ -80,6 +80,26 @@ def u64(seed: int, n: int, start: int = 0) -> np.ndarray:
     return _fill(K_U64, seed, start, np.empty(n, np.uint64))
 
 
+AFFINE, MAT2 = 5, 6  # element types of ordered products (uint64 words per element: 2, 4)
+
+
+def monoid_input(seed: int, shape, kind: int, start: int = 0) -> np.ndarray:
+    """Random elements of an ordered-product type, uint64 of shape shape + (w,).
+    Affine maps (a, b) get an odd a and 2x2 matrices an odd determinant (odd
+    diagonal, even upper-right entry), so long products stay invertible modulo
+    2^64 instead of collapsing to multiples of large powers of two."""
+    w = 2 if kind == AFFINE else 4
+    n = int(np.prod(shape, dtype=np.int64))
+    x = u64(seed, n * w, start).reshape(tuple(shape) + (w,))
+    if kind == AFFINE:
+        x[..., 0] |= np.uint64(1)
+    else:
+        x[..., 0] |= np.uint64(1)
+        x[..., 3] |= np.uint64(1)
+        x[..., 1] &= ~np.uint64(1)
+    return x
+
+
 def uniform_i32(seed: int, shape, lo: int, hi: int, start: int = 0) -> np.ndarray:
     out = np.empty(shape, np.int32)
     return _fill(K_I32, seed, start, out.reshape(-1), lo, hi).reshape(shape)
