@@ -190,6 +190,29 @@ def extra_int_workloads(steps, warmup, stream):
     return res
 
 
+def ordered_products(stream, steps=20, warmup=3):
+    """Ordered (non-commutative) products, 1 GiB each: 4096 recurrences of 16,384
+    affine steps, and 4096 products of 8,192 2x2 matrices, modulo 2^64.  The values
+    are random words (the product kernels do the same work for any value)."""
+    import numpy as np
+    import torch
+
+    import paper_2309_01906_amd as hp
+    res = {}
+    for name, dt, ext in (("affine_4096x16384", hp.AFFINE64, (4096, 16384)), ("mat2x2_4096x8192", hp.MAT2X2_64, (4096, 8192))):
+        g = torch.Generator(device="cuda").manual_seed(230901906)
+        x = torch.randint(-2**62, 2**62, (int(np.prod(ext)) * hp.WIDTH[dt],), dtype=torch.int64, device="cuda",
+                          generator=g)
+        with hp.Plan(ext, (hp.NONE, hp.PROD), dt) as p:
+            out = p.empty_out(x.device)
+            wall, ev = time_plan(p, x, out, steps, warmup, stream)
+            nb = p.info["in_bytes"] + p.info["out_bytes"]
+            res[name] = {"bytes": nb, "kernel": p.info["kernel_name"], "p50_us": round(pct(ev, 50) * 1e3, 1),
+                         "GBps": round(nb / (pct(ev, 50) * 1e-3) / 1e9, 1), "chunks_per_output": p.info["gsplit"]}
+        del x
+    return res
+
+
 def batched_vs_plain(stream, steps=20, warmup=3, plain=True):
     """10,000 uneven bf16 nests: one persistent launch replayed from a hipGraph vs one
     launch per nest (eager, and all launches captured in one graph).  Same plans, so
@@ -401,6 +424,7 @@ def main():
             line["batched_vs_plain"] = batched_vs_plain(stream)
         if not args.no_serving:
             line["serving"] = serving()
+        line["ordered_products"] = ordered_products(stream)
     plan.close()
     print(json.dumps(line), flush=True)
 

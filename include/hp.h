@@ -47,8 +47,14 @@ typedef enum hp_status {
   HP_ESTATE = 9        /* call not valid in the object's current state */
 } hp_status;
 
-/* Element types.  Inputs are I32, F32 or BF16; outputs are I32, I64, F32 or F64. */
-typedef enum hp_dtype { HP_I32 = 0, HP_F32 = 1, HP_BF16 = 2, HP_I64 = 3, HP_F64 = 4 } hp_dtype;
+/* Element types.  Inputs are I32, F32 or BF16; outputs are I32, I64, F32 or F64.
+ * AFFINE64 and MAT2X2_64 are the elements of ordered products (HP_OP_PROD), both
+ * input and output, with arithmetic modulo 2^64:
+ *   AFFINE64  : (a, b), two uint64 (16 bytes): the map x -> a x + b;
+ *   MAT2X2_64 : a 2x2 matrix of uint64, row-major (32 bytes). */
+typedef enum hp_dtype {
+  HP_I32 = 0, HP_F32 = 1, HP_BF16 = 2, HP_I64 = 3, HP_F64 = 4, HP_AFFINE64 = 5, HP_MAT2X2_64 = 6
+} hp_dtype;
 
 /* Per-level operation.  NONE levels index the output and must form a prefix of
  * the nest.  Float nests support SUM only.  ARGMIN/ARGMAX pass the winning
@@ -59,7 +65,16 @@ typedef enum hp_op {
   HP_OP_MIN = 2,
   HP_OP_MAX = 3,
   HP_OP_ARGMIN = 4,
-  HP_OP_ARGMAX = 5
+  HP_OP_ARGMAX = 5,
+  /* Ordered product of AFFINE64 / MAT2X2_64 elements: associative but not
+   * commutative, so siblings are combined strictly in iteration order (the
+   * paper notes that OpenMP reductions require commutativity, section 2):
+   *   R_m = R_{m+1}(0) * R_{m+1}(1) * ... * R_{m+1}(e_m - 1).
+   * Affine: (a1, b1) * (a2, b2) = (a1 a2, a2 b1 + b2), the first map applied
+   * first; matrices: the matrix product.  Every reducing level of such a nest
+   * is PROD; the planner chooses the map (explicit maps: HP_EUNSUPPORTED); batches
+   * and the server do not take these nests. */
+  HP_OP_PROD = 6
 } hp_op;
 
 /* Scope bits of a level map.  A level may use several adjacent scopes (a
@@ -133,7 +148,8 @@ typedef enum hp_kernel {
   HP_KERNEL_GENERIC8 = 2, /* float, depth <= 8 */
   HP_KERNEL_INT_FLAT = 3, /* int32, depth <= 4, one reducing segment */
   HP_KERNEL_INT_SEG = 4,  /* int32, depth <= 4, up to three segments */
-  HP_KERNEL_INT_DEEP = 5  /* int32, anything else */
+  HP_KERNEL_INT_DEEP = 5, /* int32, anything else */
+  HP_KERNEL_ORDERED = 6   /* ordered products of AFFINE64 / MAT2X2_64 elements */
 } hp_kernel;
 
 typedef struct hp_plan_s* hp_plan_t;

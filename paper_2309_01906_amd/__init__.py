@@ -19,12 +19,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhp.so")
 
 MAX_DEPTH = 8
-NONE, SUM, MIN, MAX, ARGMIN, ARGMAX = 0, 1, 2, 3, 4, 5
-I32, F32, BF16, I64, F64 = 0, 1, 2, 3, 4
+NONE, SUM, MIN, MAX, ARGMIN, ARGMAX, PROD = 0, 1, 2, 3, 4, 5, 6
+I32, F32, BF16, I64, F64, AFFINE64, MAT2X2_64 = 0, 1, 2, 3, 4, 5, 6
+# uint64 words per element of the ordered-product types (tensors hold them as int64)
+WIDTH = {AFFINE64: 2, MAT2X2_64: 4}
 SCOPE = {"G": 1, "W": 2, "V": 4, "L": 8}
 AXIS = {"G": 0, "W": 1, "V": 2}
 FLAG_OUT_F32, FLAG_SCALAR, FLAG_NO_XCD, FLAG_GENERIC = 0x1, 0x2, 0x4, 0x10
-OP_NAMES = {"NONE": NONE, "SUM": SUM, "MIN": MIN, "MAX": MAX, "ARGMIN": ARGMIN, "ARGMAX": ARGMAX}
+OP_NAMES = {"NONE": NONE, "SUM": SUM, "MIN": MIN, "MAX": MAX, "ARGMIN": ARGMIN, "ARGMAX": ARGMAX, "PROD": PROD}
 STATUS = ["HP_OK", "HP_EINVAL", "HP_EUNSUPPORTED", "HP_ENOMEM", "HP_EDEVICE", "HP_EAGAIN",
           "HP_ETOOBIG", "HP_ENOTREADY", "HP_ECANCELED", "HP_ESTATE"]
 
@@ -124,12 +126,14 @@ def make_map(level_map) -> LevelMap | None:
     return m
 
 
-KERNEL_LEAN, KERNEL_GENERIC4, KERNEL_GENERIC8, KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP = range(6)
+KERNEL_LEAN, KERNEL_GENERIC4, KERNEL_GENERIC8, KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP, KERNEL_ORDERED = range(7)
 
 
 def kernel_name(inf: PlanInfo) -> str:
     """Symbol of the kernel hp_run launches for a plan (as profilers print it)."""
     c = inf.chunk
+    if inf.kernel == KERNEL_ORDERED:
+        return "hp::k_ordered<2, 16>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 8>"
     if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP):
         kind = {KERNEL_INT_FLAT: "flat", KERNEL_INT_SEG: "seg", KERNEL_INT_DEEP: "deep"}[inf.kernel]
         return f"hp::k_nest_i32_{kind}<{c}>"
@@ -170,7 +174,8 @@ def _torch():
 
 def torch_out_dtype(code):
     torch = _torch()
-    return {I32: torch.int32, I64: torch.int64, F32: torch.float32, F64: torch.float64}[code]
+    return {I32: torch.int32, I64: torch.int64, F32: torch.float32, F64: torch.float64,
+            AFFINE64: torch.int64, MAT2X2_64: torch.int64}[code]
 
 
 def dtype_of(t) -> int:
@@ -207,8 +212,12 @@ class Plan:
         check(lib().hp_plan_info_get(self._h, ctypes.byref(inf)))
         self.info = _info_dict(inf)
 
+    def _out_shape(self):
+        w = WIDTH.get(self.info["out_dtype"])
+        return (self.info["n_out"],) if w is None else (self.info["n_out"], w)
+
     def empty_out(self, device):
-        return _torch().empty(self.info["n_out"], dtype=torch_out_dtype(self.info["out_dtype"]), device=device)
+        return _torch().empty(self._out_shape(), dtype=torch_out_dtype(self.info["out_dtype"]), device=device)
 
     def run(self, inp, out=None, stream=None):
         torch = _torch()
@@ -216,11 +225,16 @@ class Plan:
             raise ValueError("input must be a device tensor")
         if not inp.is_contiguous():
             raise ValueError("input must be contiguous")
-        if inp.numel() != self.info["in_elems"] or dtype_of(inp) != self.dtype:
+        w = WIDTH.get(self.dtype)
+        if w is not None:  # ordered-product elements: int64 words, w per element
+            if inp.dtype != torch.int64 or inp.numel() != self.info["in_elems"] * w:
+                raise ValueError("input does not match the planned nest")
+        elif inp.numel() != self.info["in_elems"] or dtype_of(inp) != self.dtype:
             raise ValueError("input does not match the planned nest")
         if out is None:
             out = self.empty_out(inp.device)
-        if out.numel() != self.info["n_out"] or out.dtype != torch_out_dtype(self.info["out_dtype"]):
+        if tuple(out.shape) != self._out_shape() or out.dtype != torch_out_dtype(self.info["out_dtype"]) \
+                or not out.is_contiguous():
             raise ValueError("output does not match the plan")
         check(lib().hp_run(self._h, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                            _stream_handle(stream)))

@@ -77,6 +77,8 @@ struct alignas(16) DevPlan {
   int32_t gq;                       // innermost segment spanning workgroups (0 if none)
   int32_t vlane32;                  // the lanes of a wave lie within 2^31 bytes of lane 0
   int32_t pad3;
+  int64_t ord_block;                // ordered products: elements per output
+  int64_t ord_span;                 // ordered products: elements per chunk (gsplit chunks per output)
   // innermost segment, walked as one batched stream: its levels with more than one
   // strip, outer to inner ("inner dims")
   int32_t a;                        // first level of the innermost segment

@@ -855,6 +855,9 @@ hp_status launch_nest_f32(const DevPlan& P, const DevPlan* dP, const void* in, v
                           hipStream_t st);
 hp_status launch_nest_bf16(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
                            hipStream_t st);
+// Ordered products (AFFINE64 / MAT2X2_64 elements): the chunk kernel and, for split
+// blocks, the in-order fold of the chunk products.
+hp_status launch_ordered(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, hipStream_t st);
 hp_status launch_nest_i32(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
                           hipStream_t st);
 

@@ -163,12 +163,106 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
   }
 }
 
+// Ordered products (HP_OP_PROD over AFFINE64 / MAT2X2_64 elements).  The reduced
+// block of an output is contiguous; it is cut into gsplit chunks of ord_span
+// elements, one wavefront each.  A wave walks its chunk in tiles of 64 K elements:
+// lane l multiplies its K consecutive elements, an order-keeping butterfly
+// multiplies the 64 lane products, and the tile product is appended to the
+// chunk's product.  Chunks are folded in order by a second kernel.
+static constexpr int kOrdWaves = 4;  // waves per workgroup (independent workers)
+
+static hp_status lower_ordered(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out,
+                               int force_nw) {
+  const int d = n->depth;
+  if (map_in) return fail(HP_EUNSUPPORTED, "ordered products take the planner's map only");
+  if (force_nw) return fail(HP_EUNSUPPORTED, "ordered products are not batched");
+  if (flags & ~(uint32_t)HP_FLAG_NO_XCD) return fail(HP_EINVAL, "flag bits 0x%x do not apply to ordered products", flags);
+  int p = d;
+  int64_t total = 1;
+  for (int l = 0; l < d; ++l) {
+    const int64_t e = n->extent[l];
+    const int op = n->op[l];
+    if (e < 1) return fail(HP_EINVAL, "extent[%d] = %lld < 1", l, (long long)e);
+    if (op != HP_OP_NONE && op != HP_OP_PROD)
+      return fail(HP_EUNSUPPORTED, "ordered-product elements take PROD levels only (level %d)", l);
+    if (op == HP_OP_NONE && p != d) return fail(HP_EINVAL, "NONE at level %d after a reducing level", l);
+    if (op != HP_OP_NONE && p == d) p = l;
+    if (total > (int64_t(1) << 58) / e) return fail(HP_EUNSUPPORTED, "nest has more than 2^58 elements");
+    total *= e;
+  }
+  const int es = n->dtype == HP_AFFINE64 ? 16 : 32;
+  const int K = n->dtype == HP_AFFINE64 ? 16 : 8;  // 256 bytes per lane per tile
+  DevPlan dp;
+  memset(&dp, 0, sizeof dp);
+  dp.depth = d;
+  dp.p = p;
+  dp.dtype = n->dtype;
+  dp.flags = (int32_t)flags;
+  dp.chunk = K;
+  dp.nw = kOrdWaves;
+  dp.kernel = HP_KERNEL_ORDERED;
+  dp.in_elems = total;
+  int64_t n_out = 1, block = 1;
+  for (int l = 0; l < p; ++l) n_out *= n->extent[l];
+  for (int l = p; l < d; ++l) block *= n->extent[l];
+  dp.n_out = n_out;
+  dp.ord_block = block;
+  // chunks: enough wave units to fill the chip several times over, each at least
+  // 4 tiles
+  const int64_t tile = (int64_t)kWave * K;
+  int64_t C = 1;
+  if (p < d) {
+    C = cdiv(16384, n_out);
+    const int64_t by_len = cdiv(block, 4 * tile);
+    if (C > by_len) C = by_len;
+    if (C > 4096) C = 4096;
+    if (C < 1) C = 1;
+  }
+  int64_t span = cdiv(cdiv(block, C), tile) * tile;
+  if (span < 1) span = 1;
+  C = cdiv(block, span);
+  dp.ord_span = span;
+  dp.gsplit = C;
+  dp.gmode = C > 1 ? GCOMB_UNIFORM : GCOMB_NONE;
+  const int64_t units = n_out * C;
+  int64_t grid = cdiv(units, kOrdWaves);
+  if (grid > 2048) grid = 2048;  // wave workers walk the units grid-stride
+  dp.grid = grid;
+  dp.out_kind = n->dtype;
+  hp_plan_info& I = out->info;
+  memset(&I, 0, sizeof I);
+  I.depth = d;
+  I.out_dtype = n->dtype;
+  I.n_out = n_out;
+  I.out_bytes = (size_t)n_out * es;
+  I.in_elems = total;
+  I.in_bytes = (size_t)total * es;
+  I.grid = grid;
+  I.waves = kOrdWaves;
+  I.chunk = K;
+  I.gsplit = C;
+  I.workspace_bytes = C > 1 ? (size_t)n_out * C * es : 0;
+  I.lds_bytes = 0;
+  for (int l = 0; l < d; ++l) {
+    I.scopes[l] = l < p ? HP_SCOPE_G : (l == p ? (HP_SCOPE_G | HP_SCOPE_W | HP_SCOPE_V | HP_SCOPE_L) : HP_SCOPE_L);
+    I.units[l][HP_AXIS_G] = l < p ? (uint32_t)n->extent[l] : (l == p ? (uint32_t)C : 1u);
+    I.units[l][HP_AXIS_W] = l == p ? (uint32_t)kOrdWaves : 1u;
+    I.units[l][HP_AXIS_V] = l == p ? (uint32_t)kWave : 1u;
+    I.strips[l] = l == p ? cdiv(span, tile) : 1;
+  }
+  I.nseg = p < d ? 1 : 0;
+  I.kernel = HP_KERNEL_ORDERED;
+  out->dp = dp;
+  return HP_OK;
+}
+
 hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw) {
   if (!n || !out) return fail(HP_EINVAL, "null argument");
-  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_GENERIC))
-    return fail(HP_EINVAL, "unknown flag bits 0x%x", flags);
   const int d = n->depth;
   if (d < 1 || d > kMaxDepth) return fail(HP_EINVAL, "depth %d outside [1, %d]", d, kMaxDepth);
+  if (n->dtype == HP_AFFINE64 || n->dtype == HP_MAT2X2_64) return lower_ordered(n, map_in, flags, out, force_nw);
+  if (flags & ~(uint32_t)(HP_FLAG_OUT_F32 | HP_FLAG_SCALAR | HP_FLAG_NO_XCD | HP_FLAG_GENERIC))
+    return fail(HP_EINVAL, "unknown flag bits 0x%x", flags);
   if (n->dtype != HP_I32 && n->dtype != HP_F32 && n->dtype != HP_BF16)
     return fail(HP_EINVAL, "input dtype %d is not I32, F32 or BF16", n->dtype);
   const bool is_float = n->dtype != HP_I32;
@@ -178,6 +272,7 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     const int64_t e = n->extent[l];
     const int op = n->op[l];
     if (e < 1) return fail(HP_EINVAL, "extent[%d] = %lld < 1", l, (long long)e);
+    if (op == HP_OP_PROD) return fail(HP_EUNSUPPORTED, "PROD needs AFFINE64 or MAT2X2_64 elements (level %d)", l);
     if (op < HP_OP_NONE || op > HP_OP_ARGMAX) return fail(HP_EINVAL, "op[%d] = %d unknown", l, op);
     if (op == HP_OP_NONE && p != d) return fail(HP_EINVAL, "NONE at level %d after a reducing level", l);
     if (op != HP_OP_NONE && p == d) p = l;

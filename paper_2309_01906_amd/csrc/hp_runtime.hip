@@ -32,7 +32,7 @@ extern "C" hp_status hp_plan(const hp_nest* nest, const hp_level_map* map, uint3
   p->d_dp = nullptr;
   p->d_fold = nullptr;
   std::vector<hp::FoldTask> folds;
-  hp::fold_tasks_of(p->dp, 0, folds);
+  if (p->dp.kernel != HP_KERNEL_ORDERED) hp::fold_tasks_of(p->dp, 0, folds);  // ordered products fold themselves
   p->n_fold = (int)folds.size();
   const size_t plan_bytes = (sizeof(hp::DevPlan) + 255) / 256 * 256;
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -79,13 +79,15 @@ extern "C" hp_status hp_run(hp_plan_t plan, const void* d_in, void* d_out, void*
   if (!plan) return hp::fail(HP_EINVAL, "null plan");
   if (!d_in || !d_out) return hp::fail(HP_EINVAL, "null input or output pointer");
   if (reinterpret_cast<uintptr_t>(d_in) & 15u) return hp::fail(HP_EINVAL, "input not 16-byte aligned");
-  const uintptr_t oal = (plan->info.out_dtype == HP_I64 || plan->info.out_dtype == HP_F64) ? 7u : 3u;
+  const int od = plan->info.out_dtype;
+  const uintptr_t oal = (od == HP_AFFINE64 || od == HP_MAT2X2_64) ? 15u : (od == HP_I64 || od == HP_F64) ? 7u : 3u;
   if (reinterpret_cast<uintptr_t>(d_out) & oal) return hp::fail(HP_EINVAL, "output misaligned for its type");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
     return hp::fail(HP_EINVAL, "plan was made on device %d, current device is %d", plan->device, dev);
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hp_status s;
+  if (plan->dp.kernel == HP_KERNEL_ORDERED) return hp::launch_ordered(plan->dp, plan->d_dp, d_in, d_out, plan->ws, st);
   switch (plan->dp.dtype) {
     case HP_F32: s = hp::launch_nest_f32(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st); break;
     case HP_BF16: s = hp::launch_nest_bf16(plan->dp, plan->d_dp, d_in, d_out, plan->ws, plan->info.lds_bytes, st); break;

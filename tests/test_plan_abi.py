@@ -146,3 +146,23 @@ def test_batch_plans_are_wave_tasks_of_useful_size():
     assert (nbytes / tasks).mean() > 8 << 10       # tasks carry kilobytes, not bytes
     for i, (ext, ops, dt) in zip(infos, nests):
         assert i["n_out"] == ext[0]
+
+
+def test_ordered_products_plan_and_rejections():
+    i = hp.inspect((4096, 16384), ("NONE", "PROD"), hp.AFFINE64)
+    assert i["kernel"] == hp.KERNEL_ORDERED and i["out_dtype"] == hp.AFFINE64
+    assert i["out_bytes"] == 4096 * 16 and i["in_bytes"] == 4096 * 16384 * 16
+    assert i["workspace_bytes"] == (4096 * i["gsplit"] * 16 if i["gsplit"] > 1 else 0)
+    one = hp.inspect((1, 1 << 22), ("NONE", "PROD"), hp.MAT2X2_64)
+    assert one["gsplit"] > 1 and one["workspace_bytes"] == one["gsplit"] * 32
+    # chunks cover the block exactly once
+    span = -(-(1 << 22) // one["gsplit"])
+    assert (one["gsplit"] - 1) * span < (1 << 22)
+    assert err((4, 4), ("NONE", "PROD"), hp.I32) == "HP_EUNSUPPORTED"
+    assert err((4, 4), ("NONE", "SUM"), hp.AFFINE64) == "HP_EUNSUPPORTED"
+    assert err((4, 4), ("NONE", "PROD"), hp.MAT2X2_64, m=["G", "V"]) == "HP_EUNSUPPORTED"
+    assert err((4, 4), ("NONE", "PROD"), hp.AFFINE64, flags=hp.FLAG_OUT_F32) == "HP_EINVAL"
+    assert err((4, 4), ("PROD", "NONE"), hp.AFFINE64) == "HP_EINVAL"
+    with pytest.raises(hp.HPError) as e:
+        hp.batch_inspect([((4, 4), (0, hp.PROD), hp.AFFINE64)], 0)
+    assert e.value.status_name == "HP_EUNSUPPORTED"
