@@ -2,8 +2,8 @@
 // 2x2 matrices modulo 2^64 (HP_OP_PROD).  The paper points out that OpenMP
 // reductions must be commutative (section 2); here siblings are combined strictly
 // in iteration order at every level of the hierarchy:
-//   lane    K consecutive elements multiplied in registers (a balanced tree over
-//           adjacent pairs, which keeps their order);
+//   lane    K consecutive elements (read from LDS after a coalesced load of the
+//           tile) multiplied in registers, a balanced tree over adjacent pairs;
 //   wave    a xor butterfly in which the lower-lane half always stands on the left,
 //           so after log2(64) steps every lane holds the tile's product in order;
 //   chunk   tile products appended left to right by the wave;
@@ -81,30 +81,69 @@ __device__ __forceinline__ Elem<W> shfl(const Elem<W>& a, int mask, int lane) {
   return r;
 }
 
-// Every wave is a worker: unit u = (output u / C, chunk u % C), grid-stride.
+// LDS layout of one wave's tile: 64 lane runs of 8 sixteen-byte words (K elements),
+// rows padded to 144 bytes so that the 16 lanes served together hit distinct banks.
+constexpr int kRunWords = 8;
+constexpr int kRowBytes = kRunWords * 16 + 16;
+constexpr int kWaveSlice = 64 * kRowBytes;
+__device__ __forceinline__ int word_slot(int wi) { return (wi / kRunWords) * kRowBytes + (wi % kRunWords) * 16; }
+
+// Every wave is a worker: unit u = (output u / C, chunk u % C), grid-stride.  A
+// tile is read from HBM with coalesced 16-byte loads (word q*64 + lane), staged in
+// the wave's LDS slice, and read back as one contiguous run of K elements per
+// lane.  The next tile's loads are issued before the current tile is multiplied.
 template <int W, int K>
 __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd, const u64* __restrict__ in,
                                                  u64* __restrict__ out, u64* __restrict__ ws) {
+  static_assert(K * W / 2 == kRunWords, "a lane run is 8 sixteen-byte words");
+  typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+  typedef const __attribute__((address_space(1))) u64x2 G2;
+  extern __shared__ __align__(16) char lds[];
   const DevPlan& P = *Pd;
   const int lane = (int)(threadIdx.x & 63);
+  char* slice = lds + (threadIdx.x >> 6) * kWaveSlice;
   const long long C = P.gsplit, B = P.ord_block, S = P.ord_span;
   const long long units = P.n_out * C;
   const long long nwv = (long long)gridDim.x * (blockDim.x >> 6);
   constexpr long long kTile = 64LL * K;
+  constexpr int kEw = W / 2;  // sixteen-byte words per element
+  // identity words: affine (1, 0); matrix rows (1, 0) and (0, 1)
+  auto unit_word = [](int h) -> u64x2 { return h == 0 ? u64x2{1ull, 0ull} : u64x2{0ull, 1ull}; };
   for (long long u = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < units; u += nwv) {
     const long long o = u / C, c = u - o * C;
     const u64* blk = in + (size_t)o * B * W;
     const long long lo = c * S, hi = (lo + S < B) ? lo + S : B;
+    auto fetch = [&](long long t, u64x2* g) {
+#pragma unroll
+      for (int q = 0; q < kRunWords; ++q) {
+        const int wi = q * 64 + lane;
+        const long long e = t + wi / kEw;
+        const bool ok = e < hi;
+        g[q] = __builtin_nontemporal_load((G2*)(blk + (size_t)(ok ? e : lo) * W + (wi % kEw) * 2));
+        if (!ok) g[q] = unit_word(wi % kEw);
+      }
+    };
+    u64x2 g[kRunWords];
+    fetch(lo, g);
     Elem<W> acc = unit<W>();
     for (long long t = lo; t < hi; t += kTile) {
-      // lane run: elements t + lane K + j; past the chunk end the unit element
+#pragma unroll
+      for (int q = 0; q < kRunWords; ++q) *reinterpret_cast<u64x2*>(slice + word_slot(q * 64 + lane)) = g[q];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
       Elem<W> x[K];
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const long long i = t + (long long)lane * K + j;
-        x[j] = load_elem<W>(blk + (size_t)(i < hi ? i : lo) * W);
-        if (!(i < hi)) x[j] = unit<W>();
+      for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int h = 0; h < kEw; ++h) {
+          const u64x2 v = *reinterpret_cast<const u64x2*>(slice + lane * kRowBytes + (k * kEw + h) * 16);
+          x[k].v[2 * h] = v.x;
+          x[k].v[2 * h + 1] = v.y;
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (t + kTile < hi) fetch(t + kTile, g);  // in flight while this tile is multiplied
       // the lane's K elements as a balanced tree (adjacent pairs, order kept), so
       // the multiplies of one level are independent of each other
 #pragma unroll
@@ -150,6 +189,37 @@ __global__ void __launch_bounds__(256) k_ordered_fold(const DevPlan* __restrict_
   }
 }
 
+// Many chunks per output: one wave per output, lane l folds chunks
+// [l R, (l + 1) R) in order, then the order-keeping butterfly joins the lanes.
+template <int W>
+__global__ void __launch_bounds__(256) k_ordered_fold_wave(const DevPlan* __restrict__ Pd, const u64* __restrict__ ws,
+                                                           u64* __restrict__ out) {
+  const DevPlan& P = *Pd;
+  const int lane = (int)(threadIdx.x & 63);
+  const long long C = P.gsplit, R = (C + 63) / 64;
+  const long long nwv = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long o = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); o < P.n_out; o += nwv) {
+    Elem<W> acc = unit<W>();
+    const long long c1 = (lane + 1) * R < C ? (lane + 1) * R : C;
+    for (long long c = lane * R; c < c1; ++c) {
+      Elem<W> e;
+#pragma unroll
+      for (int k = 0; k < W; ++k) e.v[k] = ws[(size_t)(o * C + c) * W + k];
+      acc = mul<W>(acc, e);
+    }
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const Elem<W> other = shfl<W>(acc, 1 << b, lane);
+      const bool low = ((lane >> b) & 1) == 0;
+      acc = mul<W>(pick<W>(low, acc, other), pick<W>(low, other, acc));
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) out[(size_t)o * W + k] = acc.v[k];
+    }
+  }
+}
+
 // A nest without reducing levels: every element is its own output.
 template <int W>
 __global__ void __launch_bounds__(256) k_ordered_copy(const DevPlan* __restrict__ Pd, const u64* __restrict__ in,
@@ -173,9 +243,15 @@ hp_status launch_ordered(const DevPlan& P, const DevPlan* dP, const void* in, vo
     else hipLaunchKernelGGL(k_ordered_copy<4>, dim3((unsigned)g), dim3(256), 0, st, dP, x, y);
   } else {
     const dim3 grid((unsigned)P.grid), block((unsigned)(P.nw * kWave));
-    if (aff) hipLaunchKernelGGL((k_ordered<2, 16>), grid, block, 0, st, dP, x, y, w);
-    else hipLaunchKernelGGL((k_ordered<4, 8>), grid, block, 0, st, dP, x, y, w);
-    if (P.gsplit > 1) {
+    const size_t lds = (size_t)P.nw * kWaveSlice;
+    if (aff) hipLaunchKernelGGL((k_ordered<2, 8>), grid, block, lds, st, dP, x, y, w);
+    else hipLaunchKernelGGL((k_ordered<4, 4>), grid, block, lds, st, dP, x, y, w);
+    if (P.gsplit > 64) {  // long folds: a wave per output
+      long long g = (P.n_out + 3) / 4;
+      if (g > 4096) g = 4096;
+      if (aff) hipLaunchKernelGGL(k_ordered_fold_wave<2>, dim3((unsigned)g), dim3(256), 0, st, dP, w, y);
+      else hipLaunchKernelGGL(k_ordered_fold_wave<4>, dim3((unsigned)g), dim3(256), 0, st, dP, w, y);
+    } else if (P.gsplit > 1) {
       long long g = (P.n_out + 255) / 256;
       if (g > 4096) g = 4096;
       if (aff) hipLaunchKernelGGL(k_ordered_fold<2>, dim3((unsigned)g), dim3(256), 0, st, dP, w, y);

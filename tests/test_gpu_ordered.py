@@ -26,7 +26,7 @@ def run_gpu(x, ext, ops, dtype):
 @pytest.mark.parametrize("kind", ["affine", "mat2"])
 @pytest.mark.parametrize("ext,nprod", [
     ((64, 5000), 1), ((5, 3, 77, 13), 3), ((1000, 1), 1), ((1, 1 << 20), 1), ((1, 100003), 1),
-    ((3, 2, 4097), 1), ((2, 3, 4), 0), ((7, 1, 1, 9), 2),
+    ((3, 2, 4097), 1), ((2, 3, 4), 0), ((7, 1, 1, 9), 2), ((3, 300007), 1),
 ])
 def test_ordered_products_match_the_oracle(kind, ext, nprod):
     dt, ok = KINDS[kind]
