@@ -110,6 +110,14 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
   while (l >= p && lanes_left > 1) {
     const int64_t need = cdiv(n->extent[l], l == d - 1 ? chunk_last : 1);
     uint64_t f = pow2ceil((uint64_t)need);
+    // An innermost level that is a segment of its own under another reducing level
+    // is combined across its lanes after every iteration of the level above: give
+    // each lane at least 4 of its chunks, so that combine runs 4 times less often.
+    if (l == d - 1 && l > p) {
+      const int a = n->op[l - 1], b = n->op[l];
+      const bool arg = a == HP_OP_ARGMIN || a == HP_OP_ARGMAX || b == HP_OP_ARGMIN || b == HP_OP_ARGMAX;
+      if ((arg || a != b) && f >= 4) f /= 4;
+    }
     if (f >= (uint64_t)lanes_left || l == p) f = (uint64_t)lanes_left;
     m->scopes[l] = HP_SCOPE_V;
     m->units[l][HP_AXIS_V] = (uint32_t)f;
