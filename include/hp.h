@@ -188,20 +188,23 @@ hp_status hp_destroy(hp_plan_t plan);
 
 /* ---------------------------------------------------------------------------
  * Batches: many nests of uneven sizes in one persistent launch per kernel family.
- * Workgroups take (nest, workgroup) tasks from one atomic counter -- a dynamic
- * schedule on the grid level (section 3.5), the one synchronisation it needs --
- * largest tasks first.  Every nest keeps the plan it would get alone (its own
- * shape and the tuner cache decide it, never the batch), so its result is the
- * same bits as a single run of that plan.
+ * Nests are planned as one-wavefront plans, and every wavefront of the persistent
+ * workgroups is an independent worker: it starts on tasks dealt to it statically
+ * and then takes (nest, workgroup) tasks from an atomic counter -- a dynamic
+ * schedule on the grid level (section 3.5).  Tasks go largest first into 8 queues,
+ * one per XCD.  Grid-split nests are folded by a second kernel after the
+ * persistent one.  Every nest keeps the plan it would get alone (its own shape and
+ * the tuner cache decide it, never the batch), so its result is the same bits as
+ * a single run of that plan.  Ordered products (HP_OP_PROD) are not batched.
  */
 typedef struct hp_batch_s* hp_batch_t;
 
 #define HP_BATCH_GRAPH 0x100u   /* hp_batch_run replays a captured hipGraph */
 #define HP_BATCH_NO_TUNE 0x200u /* ignore the tuner cache: automatic maps only */
 
-/* Plan n nests (each validated as by hp_plan_inspect; batched plans use 4 waves
- * per workgroup) and allocate the batch's device tables, task lists, counters and
- * grid-combine workspaces.  flags: HP_BATCH_GRAPH, HP_BATCH_NO_TUNE,
+/* Plan n nests (each validated as by hp_plan_inspect; batched plans use one
+ * wavefront per workgroup task) and allocate the batch's device tables, task
+ * lists, counters and grid-combine workspaces.  flags: HP_BATCH_GRAPH, HP_BATCH_NO_TUNE,
  * HP_FLAG_OUT_F32.  HP_EINVAL / HP_EUNSUPPORTED name the first
  * bad nest; HP_ENOMEM if device memory runs out. */
 hp_status hp_batch_plan(const hp_nest* nests, int64_t n, uint32_t flags, hp_batch_t* out);
