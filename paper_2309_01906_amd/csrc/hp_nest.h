@@ -645,20 +645,29 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
   };
   bool done = false;
   if constexpr (!LEAN && PF) {
-    if (P.inner_iters == 1 && P.outer_iters > 1) {
-      // The innermost segment is one chunk per outer iteration: load the chunks of
-      // UO outer iterations back to back, then fold and combine them in order.
-      auto prefetch = [&](auto opc) {
+    if (P.outer_iters > 1 && P.nid <= 1 && P.inner_iters <= 4) {
+      // The innermost segment is at most 4 chunks per outer iteration: load the
+      // chunks of UO outer iterations back to back, then fold and combine them in
+      // order, so that a wave has more than one iteration's loads in flight.
+      auto prefetch = [&](auto opc, auto fmc) {
         constexpr int OPI = decltype(opc)::value;
-        constexpr int UO = U >= 8 ? U / 2 : U;
+        constexpr int FM = decltype(fmc)::value;  // chunks per outer iteration, at most
+        constexpr int UO = FM == 1 ? (U >= 8 ? U / 2 : U) : (U / FM > 1 ? U / FM : 2);
         using V = typename Chunk<typename T::Raw, C>::V;
-              long long t_first = 0;
+        const int F = (int)P.inner_iters;
+        const long long ss = P.nid > 0 ? P.id_sstride[0] : 0;
+        const bool rag = P.nid > 0 && P.id_ragged[0];
+        const int lim = th.limc[0];
+        long long t_first = 0, span_last = 0;
 #pragma unroll
         for (int m = 0; m < KD; ++m)
-          if (m == P.depth - 1) t_first = th.targ[m];
+          if (m == P.depth - 1) {
+            t_first = th.targ[m];
+            span_last = P.last_dim_is_last_level ? P.lv[m].span : 0;
+          }
         for (long long q0 = 0; q0 < P.outer_iters; q0 += UO) {
           const int nu = (P.outer_iters - q0) < UO ? (int)(P.outer_iters - q0) : UO;
-          V x[UO];
+          V x[UO][FM];
           bool ok[UO];
           int s_keep[KD];
 #pragma unroll
@@ -669,7 +678,12 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
             ok[u] = false;
             if (u < nu) {
               ok[u] = outer_valid();
-              x[u] = load_chunk<V>(ok[u] ? in + base + soff : in);
+#pragma unroll
+              for (int f = 0; f < FM; ++f)
+                if (f < F) {
+                  const bool okf = ok[u] && (!rag || f < lim);
+                  x[u][f] = load_chunk<V>(okf ? in + base + soff + f * ss : in);
+                }
               advance();
             }
           }
@@ -680,24 +694,30 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
           for (int u = 0; u < UO; ++u) {
             if (u < nu) {
               Acc ai = T::identity(OPI);
-              AddChunk<T, C, OPI>::run(ai, x[u], t_first, ok[u]);
+#pragma unroll
+              for (int f = 0; f < FM; ++f)
+                if (f < F) AddChunk<T, C, OPI>::run(ai, x[u][f], t_first + f * span_last, ok[u] && (!rag || f < lim));
               consume(ai);
               advance();
             }
           }
         }
       };
-      if constexpr (T::kFloat) {
-        prefetch(std::integral_constant<int, HP_OP_SUM>{});
-      } else {
-        switch (P.seg[inner].op) {
-          case HP_OP_MIN: prefetch(std::integral_constant<int, HP_OP_MIN>{}); break;
-          case HP_OP_MAX: prefetch(std::integral_constant<int, HP_OP_MAX>{}); break;
-          case HP_OP_ARGMIN: prefetch(std::integral_constant<int, HP_OP_ARGMIN>{}); break;
-          case HP_OP_ARGMAX: prefetch(std::integral_constant<int, HP_OP_ARGMAX>{}); break;
-          default: prefetch(std::integral_constant<int, HP_OP_SUM>{}); break;
+      auto by_op = [&](auto fmc) {
+        if constexpr (T::kFloat) {
+          prefetch(std::integral_constant<int, HP_OP_SUM>{}, fmc);
+        } else {
+          switch (P.seg[inner].op) {
+            case HP_OP_MIN: prefetch(std::integral_constant<int, HP_OP_MIN>{}, fmc); break;
+            case HP_OP_MAX: prefetch(std::integral_constant<int, HP_OP_MAX>{}, fmc); break;
+            case HP_OP_ARGMIN: prefetch(std::integral_constant<int, HP_OP_ARGMIN>{}, fmc); break;
+            case HP_OP_ARGMAX: prefetch(std::integral_constant<int, HP_OP_ARGMAX>{}, fmc); break;
+            default: prefetch(std::integral_constant<int, HP_OP_SUM>{}, fmc); break;
+          }
         }
-      }
+      };
+      if (P.inner_iters == 1) by_op(std::integral_constant<int, 1>{});
+      else by_op(std::integral_constant<int, 4>{});
       done = true;
     }
   }
