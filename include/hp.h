@@ -338,6 +338,16 @@ hp_status hp_server_replay(hp_server_t s, int64_t n, const hp_nest* nests, const
  * slots.  NULL is a no-op. */
 hp_status hp_server_destroy(hp_server_t s);
 
+/* ---------------------------------------------------------------------------
+ * Calibration (not part of the method): a plain streaming read of `bytes` bytes
+ * at d_in -- 16-byte nontemporal loads, four in flight per thread, each workgroup
+ * reading 16 KiB blocks block-cyclically, added up -- on `grid` workgroups of 256
+ * threads.  It writes one float per workgroup to d_out
+ * (grid floats, caller-owned), only to keep the loads.  Its bandwidth is the read
+ * ceiling the reduction kernels are compared with.  d_in and bytes must be
+ * multiples of 16; asynchronous on `stream`. */
+hp_status hp_stream_read(const void* d_in, size_t bytes, float* d_out, int32_t grid, void* stream);
+
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* hp_last_error(void);
 

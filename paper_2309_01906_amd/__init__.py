@@ -84,6 +84,8 @@ def lib():
         L.hp_last_error.restype = ctypes.c_char_p
         L.hp_status_str.argtypes = [st]
         L.hp_status_str.restype = ctypes.c_char_p
+        L.hp_stream_read.argtypes = [vp, ctypes.c_size_t, vp, ctypes.c_int32, vp]
+        L.hp_stream_read.restype = st
         _lib = L
     return _lib
 
@@ -259,6 +261,15 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def stream_read(inp, scratch, grid: int, stream=None):
+    """Calibration read of the whole device tensor ``inp`` (hp_stream_read); ``scratch``
+    is a float32 device tensor of at least ``grid`` elements."""
+    if scratch.numel() < grid:
+        raise ValueError("scratch needs one float per workgroup")
+    check(lib().hp_stream_read(ctypes.c_void_p(inp.data_ptr()), inp.numel() * inp.element_size(),
+                               ctypes.c_void_p(scratch.data_ptr()), int(grid), _stream_handle(stream)))
 
 
 def reduce(inp, extents, ops, level_map=None, flags: int = 0, stream=None):

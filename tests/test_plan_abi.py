@@ -166,3 +166,10 @@ def test_ordered_products_plan_and_rejections():
     with pytest.raises(hp.HPError) as e:
         hp.batch_inspect([((4, 4), (0, hp.PROD), hp.AFFINE64)], 0)
     assert e.value.status_name == "HP_EUNSUPPORTED"
+
+
+def test_stream_read_rejects_bad_arguments_without_a_device():
+    L = hp.lib()
+    assert L.hp_stream_read(None, 1024, None, 1, None) == 1                 # HP_EINVAL: null pointers
+    assert L.hp_stream_read(16, 1000, 16, 1, None) == 1                     # size not a multiple of 16
+    assert L.hp_stream_read(16, 1024, 16, 0, None) == 1                     # grid out of range
