@@ -61,6 +61,9 @@ def _load():
         lib.oracle_abs_sum_range.restype = ctypes.c_int
         lib.oracle_prod_range.argtypes = lib.oracle_reduce_range.argtypes
         lib.oracle_prod_range.restype = ctypes.c_int
+        lib.oracle_stencil.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_stencil.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -153,6 +156,19 @@ def prod(x: np.ndarray, extents, ops, dtype, threads: int = 1, o_begin: int = 0,
                                    int(o_begin), int(o_end), int(threads))
     if rc != 0:
         raise ValueError("oracle rejected the nest or range")
+    return out
+
+
+def stencil(x: np.ndarray, steps: int, c0: float, c1: float) -> np.ndarray:
+    """`steps` five-point Jacobi sweeps of the float32 2-D array ``x`` (boundary
+    cells fixed), in double precision."""
+    if x.dtype != np.float32 or x.ndim != 2 or not x.flags.c_contiguous:
+        raise TypeError("input must be a C-contiguous 2-D float32 array")
+    out = np.empty(x.shape, np.float64)
+    rc = _load().oracle_stencil(x.shape[0], x.shape[1], int(steps), float(c0), float(c1), x.ctypes.data,
+                                out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the stencil")
     return out
 
 

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define OR_MAX_DEPTH 8
@@ -385,5 +386,42 @@ int oracle_prod_range(int depth, const int64_t* extents, const int* ops, int dty
   p_part(&parts[0]);
   for (t = started + 1; t < threads; ++t) p_part(&parts[t]);
   for (t = 1; t <= started; ++t) pthread_join(th[t], NULL);
+  return 0;
+}
+
+/* ---- stencils -------------------------------------------------------------- */
+
+int oracle_stencil(int64_t rows, int64_t cols, int steps, double c0, double c1, const float* in, double* out) {
+  int64_t i, j, n;
+  int s;
+  double *a, *b;
+  if (rows < 1 || cols < 1 || steps < 0 || !in || !out) return -1;
+  n = rows * cols;
+  a = (double*)malloc((size_t)n * sizeof(double));
+  b = (double*)malloc((size_t)n * sizeof(double));
+  if (!a || !b) {
+    free(a);
+    free(b);
+    return -1;
+  }
+  for (i = 0; i < n; ++i) a[i] = (double)in[i];
+  for (s = 0; s < steps; ++s) {
+    for (i = 0; i < rows; ++i)
+      for (j = 0; j < cols; ++j) {
+        const int64_t k = i * cols + j;
+        if (i == 0 || i == rows - 1 || j == 0 || j == cols - 1)
+          b[k] = a[k];
+        else
+          b[k] = c0 * a[k] + c1 * ((a[k - cols] + a[k + cols]) + (a[k - 1] + a[k + 1]));
+      }
+    {
+      double* t = a;
+      a = b;
+      b = t;
+    }
+  }
+  memcpy(out, a, (size_t)n * sizeof(double));
+  free(a);
+  free(b);
   return 0;
 }

@@ -83,6 +83,18 @@ enum { OR_PROD = 6 };
 int oracle_prod_range(int depth, const int64_t* extents, const int* ops, int dtype, const void* in,
                       void* out, int64_t o_begin, int64_t o_end, int threads);
 
+/* ---- stencils ----------------------------------------------------------------
+ *
+ * The paper's second class of multi-level algorithms: a stencil whose input
+ * region per unit fits that level's local memory, with a ghost surface of
+ * neighbours around it.  This one is the 2-D five-point Jacobi sweep on a
+ * rows x cols row-major array, repeated `steps` times:
+ *   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1]))
+ * for interior cells (1 <= i <= rows-2, 1 <= j <= cols-2); boundary cells keep
+ * their input value.  Computed in double precision from the float input; out
+ * receives rows*cols doubles.  Returns 0, or -1 for bad arguments. */
+int oracle_stencil(int64_t rows, int64_t cols, int steps, double c0, double c1, const float* in, double* out);
+
 #ifdef __cplusplus
 }
 #endif

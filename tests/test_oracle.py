@@ -395,3 +395,55 @@ def test_product_threads_and_ranges():
     r5 = oracle.prod(x, (50, 20), (NONE, PROD), MAT2, threads=5)
     np.testing.assert_array_equal(r1, r5)
     np.testing.assert_array_equal(oracle.prod(x, (50, 20), (NONE, PROD), MAT2, o_begin=7, o_end=19), r1[7:19])
+
+
+# ---------------------------------------------------------------------------
+# stencils: five-point Jacobi sweeps with fixed boundary cells
+
+def _np_jacobi(x, steps, c0, c1):
+    """Independent numpy version (array slices, same association)."""
+    a = x.astype(np.float64)
+    for _ in range(steps):
+        b = a.copy()
+        b[1:-1, 1:-1] = c0 * a[1:-1, 1:-1] + c1 * ((a[:-2, 1:-1] + a[2:, 1:-1]) + (a[1:-1, :-2] + a[1:-1, 2:]))
+        a = b
+    return a
+
+
+def test_stencil_linear_fields_are_fixed_points():
+    i, j = np.mgrid[0:40, 0:56]
+    x = (3 * i - 2 * j + 7).astype(np.float32)
+    for steps in (1, 4, 9):
+        np.testing.assert_array_equal(oracle.stencil(x, steps, 0.5, 0.125), x.astype(np.float64))
+
+
+def test_stencil_quadratic_field_grows_by_the_laplacian():
+    """A = i^2 + j^2 has Laplacian 4: each sweep adds 4 c1 wherever the sweep cone
+    of the cell stays inside the interior."""
+    i, j = np.mgrid[0:48, 0:48]
+    x = (i * i + j * j).astype(np.float32)
+    c0, c1, T = 0.5, 0.125, 5
+    got = oracle.stencil(x, T, c0, c1)
+    inner = (slice(T, 48 - T), slice(T, 48 - T))
+    np.testing.assert_array_equal(got[inner], x[inner].astype(np.float64) + 4 * c1 * T)
+
+
+def test_stencil_impulse_and_boundary():
+    x = np.zeros((11, 13), np.float32)
+    x[5, 6] = 1.0
+    x[0, :] = 3.0  # boundary row: stays
+    got = oracle.stencil(x, 1, 0.25, 0.1875)
+    assert got[5, 6] == 0.25
+    for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        assert got[5 + di, 6 + dj] == 0.1875
+    np.testing.assert_array_equal(got[0, :], 3.0)
+    assert got[1, 6] == 0.1875 * 3.0  # the boundary row feeds its interior neighbour
+    np.testing.assert_array_equal(oracle.stencil(x, 0, 0.25, 0.1875), x.astype(np.float64))
+
+
+def test_stencil_matches_an_independent_evaluation():
+    x = workloads.normal_f32(120, (37, 61))
+    for steps in (1, 3, 8):
+        np.testing.assert_array_equal(oracle.stencil(x, steps, 0.6, 0.1), _np_jacobi(x, steps, 0.6, 0.1))
+    tiny = workloads.normal_f32(121, (2, 9))  # no interior: unchanged
+    np.testing.assert_array_equal(oracle.stencil(tiny, 4, 0.6, 0.1), tiny.astype(np.float64))
