@@ -213,6 +213,42 @@ def ordered_products(stream, steps=20, warmup=3):
     return res
 
 
+def stencils(stream, steps=20, warmup=3):
+    """Five-point Jacobi sweeps of an 8192 x 8192 fp32 array (256 MiB), 1, 4 and 8
+    sweeps per launch, tiled through LDS with a ghost surface.  `effective_GBps`
+    counts one read and one write of every cell per sweep (what separate sweeps
+    would move); `hbm_GBps` counts what one launch moves: the 32 x 64 tiles with
+    their ghost cells read once, the array written once."""
+    import torch
+
+    import paper_2309_01906_amd as hp
+    import workloads
+    R = C = 8192
+    x = torch.from_numpy(workloads.normal_f32(230901906 + 7, (R, C))).cuda()
+    y = torch.empty_like(x)
+    res = {}
+    for t in (1, 4, 8):
+        with hp.Stencil(R, C, t, 0.6, 0.1) as st:
+            for _ in range(warmup):
+                st.run(x, y, stream)
+            torch.cuda.synchronize()
+            ev = []
+            for _ in range(steps):
+                s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s_.record(stream)
+                st.run(x, y, stream)
+                e_.record(stream)
+                e_.synchronize()
+                ev.append(s_.elapsed_time(e_))
+        us = pct(ev, 50) * 1e3
+        amp = (32 + 2 * t) * (64 + 2 * t) / (32 * 64)
+        res[f"sweeps_{t}"] = {"p50_us": round(us, 1),
+                              "effective_GBps": round(8.0 * R * C * t / us / 1e3, 1),
+                              "hbm_GBps": round((4.0 * amp + 4.0) * R * C / us / 1e3, 1)}
+    del x, y
+    return res
+
+
 def batched_vs_plain(stream, steps=20, warmup=3, plain=True):
     """10,000 uneven bf16 nests: one persistent launch replayed from a hipGraph vs one
     launch per nest (eager, and all launches captured in one graph).  Same plans, so
@@ -445,6 +481,7 @@ def main():
         if not args.no_serving:
             line["serving"] = serving()
         line["ordered_products"] = ordered_products(stream)
+        line["stencils"] = stencils(stream)
     plan.close()
     print(json.dumps(line), flush=True)
 

@@ -339,6 +339,25 @@ hp_status hp_server_replay(hp_server_t s, int64_t n, const hp_nest* nests, const
 hp_status hp_server_destroy(hp_server_t s);
 
 /* ---------------------------------------------------------------------------
+ * Stencils (the paper's second class of multi-level algorithms, section 4: a
+ * region whose input fits a level's local memory, repeated on every level with
+ * local memory; section 6: array sections that overlap by a ghost surface).
+ * `steps` five-point Jacobi sweeps of a rows x cols row-major float array,
+ *   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1]))
+ * for 1 <= i <= rows-2, 1 <= j <= cols-2 (fp32, in exactly this order, no fused
+ * multiply-add); boundary cells keep their values.  Every workgroup reads its
+ * 32 x 64 output tile plus a ghost surface `steps` cells wide into LDS once, runs
+ * all sweeps there and writes the tile once.
+ * hp_stencil_plan: rows, cols >= 1 (HP_EINVAL), 1 <= steps <= 8 (HP_EUNSUPPORTED).
+ * hp_stencil_run: d_in and d_out are caller-owned device arrays of rows*cols
+ * floats, 4-byte aligned, not overlapping (HP_EINVAL); asynchronous on `stream`.
+ */
+typedef struct hp_stencil_s* hp_stencil_t;
+hp_status hp_stencil_plan(int64_t rows, int64_t cols, int32_t steps, float c0, float c1, hp_stencil_t* out);
+hp_status hp_stencil_run(hp_stencil_t s, const float* d_in, float* d_out, void* stream);
+hp_status hp_stencil_destroy(hp_stencil_t s);
+
+/* ---------------------------------------------------------------------------
  * Calibration (not part of the method): a plain streaming read of `bytes` bytes
  * at d_in -- 16-byte nontemporal loads, four in flight per thread, each workgroup
  * reading 16 KiB blocks block-cyclically, added up -- on `grid` workgroups of 256

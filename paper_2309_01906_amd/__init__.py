@@ -263,6 +263,44 @@ class Plan:
         self.close()
 
 
+class Stencil:
+    """`steps` five-point Jacobi sweeps of a 2-D float32 device array, tiled through
+    LDS with a ghost surface (hp_stencil_*)."""
+
+    def __init__(self, rows: int, cols: int, steps: int, c0: float, c1: float):
+        L = lib()
+        L.hp_stencil_plan.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+        L.hp_stencil_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.hp_stencil_destroy.argtypes = [ctypes.c_void_p]
+        self._h = ctypes.c_void_p()
+        self.shape = (int(rows), int(cols))
+        check(L.hp_stencil_plan(int(rows), int(cols), int(steps), float(c0), float(c1), ctypes.byref(self._h)))
+
+    def run(self, inp, out=None, stream=None):
+        torch = _torch()
+        if inp.dtype != torch.float32 or tuple(inp.shape) != self.shape or not inp.is_contiguous():
+            raise ValueError("input must be a contiguous float32 array of the planned shape")
+        if out is None:
+            out = torch.empty_like(inp)
+        if out.dtype != torch.float32 or tuple(out.shape) != self.shape or not out.is_contiguous():
+            raise ValueError("output does not match the plan")
+        check(lib().hp_stencil_run(self._h, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            check(lib().hp_stencil_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def stream_read(inp, scratch, grid: int, stream=None):
     """Calibration read of the whole device tensor ``inp`` (hp_stream_read); ``scratch``
     is a float32 device tensor of at least ``grid`` elements."""

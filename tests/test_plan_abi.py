@@ -173,3 +173,17 @@ def test_stream_read_rejects_bad_arguments_without_a_device():
     assert L.hp_stream_read(None, 1024, None, 1, None) == 1                 # HP_EINVAL: null pointers
     assert L.hp_stream_read(16, 1000, 16, 1, None) == 1                     # size not a multiple of 16
     assert L.hp_stream_read(16, 1024, 16, 0, None) == 1                     # grid out of range
+
+
+def test_stencil_plan_rejections():
+    with pytest.raises(hp.HPError) as e:
+        hp.Stencil(0, 10, 1, 0.5, 0.125)
+    assert e.value.status_name == "HP_EINVAL"
+    with pytest.raises(hp.HPError) as e:
+        hp.Stencil(10, 10, 9, 0.5, 0.125)
+    assert e.value.status_name == "HP_EUNSUPPORTED"
+    s = hp.Stencil(100, 200, 4, 0.5, 0.125)
+    L = hp.lib()
+    assert L.hp_stencil_run(s._h, None, None, None) == 1          # null arrays
+    assert L.hp_stencil_run(s._h, 4096, 4096 + 64, None) == 1     # overlapping arrays
+    s.close()
