@@ -38,12 +38,21 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
   const int tid = (int)threadIdx.x;
   // the tile and its ghost surface; cells outside the array are never read by an
   // updated cell (only interior cells change, and their neighbours are inside)
-  for (int k = tid; k < G::H * G::W; k += kThreads) {
+  // all of a thread's loads are issued before the first one is stored to LDS
+  constexpr int kLoads = (G::H * G::W + kThreads - 1) / kThreads;
+  float v[kLoads];
+#pragma unroll
+  for (int u = 0; u < kLoads; ++u) {
+    const int k = tid + u * kThreads;
     const int r = k / G::W, c = k - (k / G::W) * G::W;
     const long long gi = i0 + r, gj = j0 + c;
-    float v = 0.f;
-    if (gi >= 0 && gi < R && gj >= 0 && gj < C) v = in[gi * C + gj];
-    buf0[r * G::P + c] = v;
+    const bool ok = k < G::H * G::W && gi >= 0 && gi < R && gj >= 0 && gj < C;
+    v[u] = ok ? in[ok ? gi * C + gj : 0] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < kLoads; ++u) {
+    const int k = tid + u * kThreads;
+    if (k < G::H * G::W) buf0[(k / G::W) * G::P + (k - (k / G::W) * G::W)] = v[u];
   }
   __syncthreads();
 #pragma unroll
