@@ -20,8 +20,6 @@
 
 struct hp_batch_s;
 namespace hp {
-hp_status launch_single(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds,
-                        hipStream_t st);
 hp_status batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags, hp_batch_s** out);
 }
 
@@ -236,47 +234,6 @@ struct Timed {
   hp::Recipe r;
   double us;
 };
-
-// median device time of `reps` runs of one candidate plan (single-nest kernel)
-hp_status time_candidate(const hp::Lowered& L, const void* in, void* out, int reps, hipStream_t st, double* us) {
-  hp::DevPlan* dP = nullptr;
-  void* ws = nullptr;
-  hipEvent_t e0, e1;
-  if (hipMalloc(&dP, sizeof(hp::DevPlan)) != hipSuccess) return hp::fail(HP_ENOMEM, "tuner plan allocation");
-  if (hipMemcpy(dP, &L.dp, sizeof(hp::DevPlan), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(dP);
-    return hp::fail(HP_EDEVICE, "tuner plan upload");
-  }
-  if (L.info.workspace_bytes) {
-    if (hipMalloc(&ws, L.info.workspace_bytes) != hipSuccess ||
-        hipMemset(ws, 0, L.info.workspace_bytes) != hipSuccess) {
-      (void)hipFree(dP);
-      if (ws) (void)hipFree(ws);
-      return hp::fail(HP_ENOMEM, "tuner workspace allocation");
-    }
-  }
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  std::vector<float> t;
-  hp_status s = HP_OK;
-  for (int r = 0; r < reps + 2 && s == HP_OK; ++r) {
-    (void)hipEventRecord(e0, st);
-    s = hp::launch_single(L.dp, dP, in, out, ws, L.info.lds_bytes, st);
-    (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) s = hp::fail(HP_EDEVICE, "tuner run failed");
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (r >= 2) t.push_back(ms);
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(dP);
-  if (ws) (void)hipFree(ws);
-  if (s != HP_OK) return s;
-  std::sort(t.begin(), t.end());
-  *us = t.empty() ? 0.0 : 1e3 * (double)t[t.size() / 2];
-  return HP_OK;
-}
 
 // Throughput of a candidate inside a batch: R replicas of the plan (distinct input
 // and output slots) as one persistent launch; returns the median time per nest.
