@@ -122,7 +122,7 @@ typedef struct hp_level_map {
 /* What the planner decided; filled by hp_plan_inspect / hp_plan_info. */
 typedef struct hp_plan_info {
   int32_t depth;
-  int32_t out_dtype;               /* HP_I32 / HP_I64 / HP_F32 / HP_F64 */
+  int32_t out_dtype;               /* HP_I32 / HP_I64 / HP_F32 / HP_F64, or the element type of an ordered product */
   int64_t n_out;                   /* number of outputs */
   size_t out_bytes;                /* n_out * size of out_dtype */
   int64_t in_elems;                /* elements of the input */
@@ -174,10 +174,13 @@ hp_status hp_plan_info_get(hp_plan_t plan, hp_plan_info* info);
 
 /* Run the nest: d_in is a device pointer to the row-major input (16-byte
  * aligned, in_bytes long), d_out a device pointer to n_out outputs of
- * out_dtype (8-byte aligned).  stream is a hipStream_t (NULL: the null
- * stream).  Asynchronous: allocates nothing and does not synchronise, so it
- * may be captured in a hipGraph.  A plan must not run on two streams at once
- * (its workspace is shared); consecutive runs on one stream are fine.
+ * out_dtype (aligned to the output element: 4 or 8 bytes, 16 for ordered
+ * products).  stream is a hipStream_t (NULL: the null stream).  Asynchronous:
+ * allocates nothing and does not synchronise, so it may be captured in a
+ * hipGraph.  A grid-split plan (gsplit > 1) launches a second, small kernel that
+ * folds the workgroups' partials in a fixed order.  A plan must not run on two
+ * streams at once (its workspace is shared); consecutive runs on one stream are
+ * fine.
  * Errors: HP_EINVAL (null plan or pointer, misalignment), HP_EDEVICE
  * (launch failure). */
 hp_status hp_run(hp_plan_t plan, const void* d_in, void* d_out, void* stream);
