@@ -55,6 +55,14 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
     if (k < G::H * G::W) buf0[(k / G::W) * G::P + (k - (k / G::W) * G::W)] = v[u];
   }
   __syncthreads();
+  // interior cells (global 1..R-2, 1..C-2) in tile-local coordinates, clamped to the
+  // region, so that the per-cell test is four 32-bit compares
+  auto local = [](long long lo_global, long long origin, int extent) -> int {
+    const long long v = lo_global - origin;
+    return (int)(v < -1 ? -1 : (v > extent ? extent : v));
+  };
+  const int ilo = local(1, i0, G::H), ihi = local(R - 2, i0, G::H);
+  const int jlo = local(1, j0, G::W), jhi = local(C - 2, j0, G::W);
 #pragma unroll
   for (int s = 1; s <= T; ++s) {
     const float* src = (s & 1) ? buf0 : buf1;
@@ -70,8 +78,7 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
       const int rb = k / wr;
       const int c = s + (k - rb * wr);
       const int r0 = s + rb * kRB;
-      const long long gj = j0 + c;
-      const bool col_in = gj >= 1 && gj <= C - 2;
+      const bool col_in = c >= jlo && c <= jhi;
       float up = src[(r0 - 1) * G::P + c];
       float mid = src[r0 * G::P + c];
 #pragma unroll
@@ -80,9 +87,8 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
         if (r < s + hr) {
           const int q = r * G::P + c;
           const float dn = src[q + G::P];
-          const long long gi = i0 + r;
           float v = mid;
-          if (col_in && gi >= 1 && gi <= R - 2) v = c0 * mid + c1 * ((up + dn) + (src[q - 1] + src[q + 1]));
+          if (col_in && r >= ilo && r <= ihi) v = c0 * mid + c1 * ((up + dn) + (src[q - 1] + src[q + 1]));
           dst[q] = v;
           up = mid;
           mid = dn;
