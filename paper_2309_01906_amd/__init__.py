@@ -135,7 +135,7 @@ def kernel_name(inf: PlanInfo) -> str:
     """Symbol of the kernel hp_run launches for a plan (as profilers print it)."""
     c = inf.chunk
     if inf.kernel == KERNEL_ORDERED:
-        return "hp::k_ordered<2, 8>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 4>"
+        return "hp::k_ordered<2, 8>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 8>"
     if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP):
         kind = {KERNEL_INT_FLAT: "flat", KERNEL_INT_SEG: "seg", KERNEL_INT_DEEP: "deep"}[inf.kernel]
         return f"hp::k_nest_i32_{kind}<{c}>"

@@ -81,12 +81,14 @@ __device__ __forceinline__ Elem<W> shfl(const Elem<W>& a, int mask, int lane) {
   return r;
 }
 
-// LDS layout of one wave's tile: 64 lane runs of 8 sixteen-byte words (K elements),
-// rows padded to 144 bytes so that the 16 lanes served together hit distinct banks.
-constexpr int kRunWords = 8;
-constexpr int kRowBytes = kRunWords * 16 + 16;
-constexpr int kWaveSlice = 64 * kRowBytes;
-__device__ __forceinline__ int word_slot(int wi) { return (wi / kRunWords) * kRowBytes + (wi % kRunWords) * 16; }
+// LDS layout of one wave's tile: 64 lane runs of RW sixteen-byte words (K elements),
+// rows padded by 16 bytes so that the 16 lanes served together hit distinct banks.
+template <int RW>
+struct Slice {
+  static constexpr int kRowBytes = RW * 16 + 16;
+  static constexpr int kBytes = 64 * kRowBytes;
+  __device__ static __forceinline__ int word_slot(int wi) { return (wi / RW) * kRowBytes + (wi % RW) * 16; }
+};
 
 // Every wave is a worker: unit u = (output u / C, chunk u % C), grid-stride.  A
 // tile is read from HBM with coalesced 16-byte loads (word q*64 + lane), staged in
@@ -95,7 +97,10 @@ __device__ __forceinline__ int word_slot(int wi) { return (wi / kRunWords) * kRo
 template <int W, int K>
 __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd, const u64* __restrict__ in,
                                                  u64* __restrict__ out, u64* __restrict__ ws) {
-  static_assert(K * W / 2 == kRunWords, "a lane run is 8 sixteen-byte words");
+  constexpr int kRunWords = K * W / 2;  // sixteen-byte words per lane run
+  using SL = Slice<kRunWords>;
+  constexpr int kRowBytes = SL::kRowBytes;
+  constexpr int kWaveSlice = SL::kBytes;
   typedef u64 u64x2 __attribute__((ext_vector_type(2)));
   typedef const __attribute__((address_space(1))) u64x2 G2;
   extern __shared__ __align__(16) char lds[];
@@ -128,7 +133,7 @@ __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd,
     Elem<W> acc = unit<W>();
     for (long long t = lo; t < hi; t += kTile) {
 #pragma unroll
-      for (int q = 0; q < kRunWords; ++q) *reinterpret_cast<u64x2*>(slice + word_slot(q * 64 + lane)) = g[q];
+      for (int q = 0; q < kRunWords; ++q) *reinterpret_cast<u64x2*>(slice + SL::word_slot(q * 64 + lane)) = g[q];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __builtin_amdgcn_wave_barrier();
       Elem<W> x[K];
@@ -243,9 +248,13 @@ hp_status launch_ordered(const DevPlan& P, const DevPlan* dP, const void* in, vo
     else hipLaunchKernelGGL(k_ordered_copy<4>, dim3((unsigned)g), dim3(256), 0, st, dP, x, y);
   } else {
     const dim3 grid((unsigned)P.grid), block((unsigned)(P.nw * kWave));
-    const size_t lds = (size_t)P.nw * kWaveSlice;
-    if (aff) hipLaunchKernelGGL((k_ordered<2, 8>), grid, block, lds, st, dP, x, y, w);
-    else hipLaunchKernelGGL((k_ordered<4, 4>), grid, block, lds, st, dP, x, y, w);
+    if (aff) {
+      const size_t lds = (size_t)P.nw * Slice<8>::kBytes;
+      hipLaunchKernelGGL((k_ordered<2, 8>), grid, block, lds, st, dP, x, y, w);
+    } else {
+      const size_t lds = (size_t)P.nw * Slice<16>::kBytes;
+      hipLaunchKernelGGL((k_ordered<4, 8>), grid, block, lds, st, dP, x, y, w);
+    }
     if (P.gsplit > 64) {  // long folds: a wave per output
       long long g = (P.n_out + 3) / 4;
       if (g > 4096) g = 4096;

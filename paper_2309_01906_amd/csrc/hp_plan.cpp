@@ -199,7 +199,7 @@ static hp_status lower_ordered(const hp_nest* n, const hp_level_map* map_in, uin
     total *= e;
   }
   const int es = n->dtype == HP_AFFINE64 ? 16 : 32;
-  const int K = n->dtype == HP_AFFINE64 ? 8 : 4;  // 128 bytes per lane per tile
+  const int K = 8;  // elements per lane run: 128 (affine) or 256 (matrices) bytes per lane per tile
   DevPlan dp;
   memset(&dp, 0, sizeof dp);
   dp.depth = d;
@@ -250,7 +250,7 @@ static hp_status lower_ordered(const hp_nest* n, const hp_level_map* map_in, uin
   I.chunk = K;
   I.gsplit = C;
   I.workspace_bytes = C > 1 ? (size_t)n_out * C * es : 0;
-  I.lds_bytes = (size_t)kOrdWaves * (64 * 144);  // one staged tile per wave
+  I.lds_bytes = (size_t)kOrdWaves * 64 * (K * es + 16);  // one staged tile per wave
   for (int l = 0; l < d; ++l) {
     I.scopes[l] = l < p ? HP_SCOPE_G : (l == p ? (HP_SCOPE_G | HP_SCOPE_W | HP_SCOPE_V | HP_SCOPE_L) : HP_SCOPE_L);
     I.units[l][HP_AXIS_G] = l < p ? (uint32_t)n->extent[l] : (l == p ? (uint32_t)C : 1u);
