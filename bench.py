@@ -64,9 +64,9 @@ def time_plan(plan, dev_in, out, steps, warmup, stream):
     return wall, ev_ms
 
 
-def traffic_from_profiles(per_launch_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources; else None."""
+def counters_from_profiles():
+    """The committed rocprofv3 counter summary of the headline kernel, if it was taken
+    on the current kernel sources; else None."""
     p = COUNTERS_JSON
     if not os.path.exists(p):
         return None
@@ -76,13 +76,34 @@ def traffic_from_profiles(per_launch_bytes):
         return None
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("traffic_bytes_per_launch")
+    return d
+
+
+def traffic_from_profiles(per_launch_bytes):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    d = counters_from_profiles()
+    return None if d is None else d.get("traffic_bytes_per_launch")
+
+
+def utilisation_from_profiles(avg_ms):
+    """VALU and LDS figures of the headline kernel: per-wave instruction counts from
+    the committed SQ counters, and the share of the SIMDs' issue time the VALU work
+    takes at this run's measured kernel time (a wave64 instruction occupies a 16-lane
+    SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz)."""
+    d = counters_from_profiles()
+    if d is None or "sq" not in d:
+        return None
+    sq = d["sq"]
+    valu = sq.get("sq_insts_valu_per_wave", 0.0) * sq["waves"]
+    return {"valu_insts_per_wave": sq.get("sq_insts_valu_per_wave"), "lds_insts_per_wave": sq.get("sq_insts_lds_per_wave"),
+            "lds_bank_conflict_cycles_per_wave": sq.get("sq_lds_bank_conflict_per_wave"),
+            "valu_share": round(valu * 4 / (1024 * 2.4e9 * avg_ms * 1e-3), 3)}
 
 
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "c2_nest_counters.json")
 
 
-def ingest_counters(fetch_csv, write_csv, kernel, nbytes, copy_bytes=1 << 30):
+def ingest_counters(fetch_csv, write_csv, kernel, nbytes, copy_bytes=1 << 30, sq_csv=None):
     """Turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch) of a `bench.py --copy-calib` run into HBM bytes
     per launch of `kernel`.  Each counter is scaled by what it reads for the 1 GiB
@@ -113,6 +134,20 @@ def ingest_counters(fetch_csv, write_csv, kernel, nbytes, copy_bytes=1 << 30):
     d = {"kernel": kernel, "kernel_hash": kernel_hash(), "algorithmic_bytes_per_launch": nbytes,
          "traffic_bytes_per_launch": traffic, "traffic_over_algorithmic": round(traffic / nbytes, 5),
          "counters": res, "calibration": f"device copy of {copy_bytes} bytes (reads and writes that many)"}
+    if sq_csv:  # per-wave instruction counts (SQ block) of the same kernel
+        sums, n = {}, {}
+        with open(sq_csv) as fh:
+            for r in csv.DictReader(fh):
+                if kernel in r["Kernel_Name"]:
+                    c = r["Counter_Name"]
+                    sums[c] = sums.get(c, 0.0) + float(r["Counter_Value"])
+                    n[c] = n.get(c, 0) + 1
+        if "SQ_WAVES" in sums:
+            waves = sums["SQ_WAVES"] / n["SQ_WAVES"]
+            d["sq"] = {"waves": waves}
+            for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_LDS_BANK_CONFLICT"):
+                if c in sums:
+                    d["sq"][c.lower() + "_per_wave"] = round(sums[c] / n[c] / waves, 2)
     os.makedirs(os.path.dirname(COUNTERS_JSON), exist_ok=True)
     with open(COUNTERS_JSON, "w") as fh:
         json.dump(d, fh, indent=1)
@@ -383,15 +418,19 @@ def main():
                     help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the persistent batched run of the 10,000-nest workload (for profiling)")
-    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="host only: write the traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--ingest-counters", nargs="+", metavar="CSV",
+                    help="host only: FETCH_SIZE csv, WRITE_SIZE csv[, SQ counters csv] of rocprofv3 --pmc "
+                         "runs -> the counter summary the bench reads; then exit")
     args = ap.parse_args()
     if args.ingest_counters:
         import paper_2309_01906_amd as hp
         import workloads
         info = hp.inspect(workloads.C2.extents, workloads.C2.ops, workloads.C2.dtype)
+        if len(args.ingest_counters) not in (2, 3):
+            raise SystemExit("--ingest-counters takes FETCH_CSV WRITE_CSV [SQ_CSV]")
         ingest_counters(args.ingest_counters[0], args.ingest_counters[1], info["kernel_name"],
-                        info["in_bytes"] + info["out_bytes"])
+                        info["in_bytes"] + info["out_bytes"],
+                        sq_csv=args.ingest_counters[2] if len(args.ingest_counters) == 3 else None)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -465,7 +504,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic_from_profiles(nbytes),
                      "kernel": plan.info["kernel_name"], "algorithmic_bytes_per_launch": nbytes,
-                     "kernel_hash": kernel_hash()},
+                     "kernel_hash": kernel_hash(), "utilisation": utilisation_from_profiles(avg_ev)},
     }
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(x_host, nest.extents, nest.ops, got)
