@@ -271,10 +271,24 @@ struct AddChunk<FloatT<uint16_t>, 1, OP> {
 template <int OP>
 struct AddChunk<IntT, 4, OP> {
   __device__ static __forceinline__ void run(IAcc& a, i32x4 x, long long t, bool ok) {
-    IntT::add(a, masked_i<OP>(x.x, ok), t, OP);
-    IntT::add(a, masked_i<OP>(x.y, ok), t + 1, OP);
-    IntT::add(a, masked_i<OP>(x.z, ok), t + 2, OP);
-    IntT::add(a, masked_i<OP>(x.w, ok), t + 3, OP);
+    if constexpr (OP == HP_OP_MIN || OP == HP_OP_MAX || OP == HP_OP_ARGMIN || OP == HP_OP_ARGMAX) {
+      // min/max are associative and commutative, and so is the lexicographic
+      // (value, index) order of ARG: reduce the four elements in 32 bits first
+      // (the smallest position among equal values), then merge once into the
+      // 64-bit carrier
+      constexpr bool mn = OP == HP_OP_MIN || OP == HP_OP_ARGMIN;
+      const int x0 = masked_i<OP>(x.x, ok), x1 = masked_i<OP>(x.y, ok);
+      const int x2 = masked_i<OP>(x.z, ok), x3 = masked_i<OP>(x.w, ok);
+      const int m = mn ? min(min(x0, x1), min(x2, x3)) : max(max(x0, x1), max(x2, x3));
+      int pos = 0;
+      if constexpr (OP == HP_OP_ARGMIN || OP == HP_OP_ARGMAX) pos = x0 == m ? 0 : x1 == m ? 1 : x2 == m ? 2 : 3;
+      IntT::add(a, m, t + pos, OP);
+    } else {
+      IntT::add(a, masked_i<OP>(x.x, ok), t, OP);
+      IntT::add(a, masked_i<OP>(x.y, ok), t + 1, OP);
+      IntT::add(a, masked_i<OP>(x.z, ok), t + 2, OP);
+      IntT::add(a, masked_i<OP>(x.w, ok), t + 3, OP);
+    }
   }
 };
 template <int OP>
@@ -787,7 +801,9 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
       const uint32_t uw = ((uint32_t)th.w >> L.wsh) & (uint32_t)(L.wf - 1);
       const uint32_t uv = ((uint32_t)th.lane >> L.vsh) & (uint32_t)(L.vf - 1);
       const long long t0 = (long long)(((unsigned long long)ug * L.wf + uw) * L.vf + uv) * L.chunk;
-      th.lim[m] = t0 < L.e ? (int)((L.e - t0 + L.span - 1) / L.span) : 0;
+      // a level without a ragged tail has every strip in range (t0 < span), and
+      // lim is only read for ragged levels: skip the per-lane division there
+      th.lim[m] = !L.ragged ? (int)L.strips : t0 < L.e ? (int)((L.e - t0 + L.span - 1) / L.span) : 0;
       th.targ[m] = (int)t0;
       if (m < P.p) {
         base_none += t0 * L.stride;
