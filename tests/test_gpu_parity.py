@@ -229,6 +229,25 @@ def test_argmin_ties_first_occurrence():
         assert_match(got, x, ext, ops, what=f"ties {ext}")
 
 
+@pytest.mark.parametrize("fill", ["max", "min"])
+def test_arg_rows_of_extreme_values(fill):
+    """Rows made only of the value a masked-out lane folds in (INT32_MAX under
+    MIN / ARGMIN, INT32_MIN under MAX / ARGMAX), beside random rows, with ragged
+    tails and chunk-internal ties: the first position of the row must still win."""
+    v = np.iinfo(np.int32).max if fill == "max" else np.iinfo(np.int32).min
+    op, argop = ("MIN", "ARGMIN") if fill == "max" else ("MAX", "ARGMAX")
+    cases = [((5, 67), ("NONE", argop)), ((3, 1001), ("NONE", argop)), ((6, 4096), ("NONE", argop)),
+             ((2, 3, 5, 131), ("NONE", "SUM", op, argop)), ((64, 7, 3, 13), ("NONE", "SUM", op, argop)),
+             ((4, 9, 64, 64), ("NONE", "SUM", op, argop)), ((7, 33), ("NONE", op))]
+    for ext, ops in cases:
+        say("case extreme rows", fill, ext, ops)
+        x = workloads.uniform_i32(77, ext, -3, 3)
+        rows = x.reshape(-1, ext[-1])
+        rows[::2] = v
+        got, _ = gpu_reduce(x, ext, ops)
+        assert_match(got, x, ext, ops, what=f"extreme {fill} {ext} {ops}")
+
+
 def test_flags_scalar_out_f32_noxcd_generic():
     import paper_2309_01906_amd as hp
     x = workloads.normal_f32(73, (256, 4096))
