@@ -196,7 +196,7 @@ hp_status hp_destroy(hp_plan_t plan);
  * and then takes (nest, workgroup) tasks from an atomic counter -- a dynamic
  * schedule on the grid level (section 3.5).  Tasks go largest first into 8 queues,
  * one per XCD.  Grid-split nests are folded by a second kernel after the
- * persistent one.  Every nest keeps the plan it would get alone (its own shape and
+ * persistent one, which also resets the task counters for the next run.  Every nest keeps the plan it would get alone (its own shape and
  * the tuner cache decide it, never the batch), so its result is the same bits as
  * a single run of that plan.  Ordered products (HP_OP_PROD) are not batched.
  */

@@ -67,7 +67,10 @@ __device__ __forceinline__ void fold_body(const DevPlan* plans, const FoldTask* 
 }
 
 __global__ void __launch_bounds__(256) k_fold(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
-                                              unsigned char* const* wss) {
+                                              unsigned char* const* wss, unsigned int* ctr, int n_ctr) {
+  // the persistent launches before this one on the stream have finished: nothing
+  // reads their task counters any more
+  for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n_ctr; i += (int)(gridDim.x * blockDim.x)) ctr[i] = 0u;
   fold_body<false>(plans, tasks, n, outs, wss, nullptr, nullptr);
 }
 
@@ -82,9 +85,9 @@ static unsigned fold_grid(int n) {
 }
 
 hp_status launch_fold(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
-                      unsigned char* const* wss, hipStream_t st) {
-  if (n <= 0) return HP_OK;
-  hipLaunchKernelGGL(k_fold, dim3(fold_grid(n)), dim3(256), 0, st, plans, tasks, n, outs, wss);
+                      unsigned char* const* wss, hipStream_t st, unsigned int* ctr, int n_ctr) {
+  if (n <= 0 && n_ctr <= 0) return HP_OK;
+  hipLaunchKernelGGL(k_fold, dim3(fold_grid(n)), dim3(256), 0, st, plans, tasks, n, outs, wss, ctr, n_ctr);
   if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "fold launch failed");
   return HP_OK;
 }
@@ -111,7 +114,7 @@ hp_status warm_batch_kernels(hipStream_t st) {
     if (s != HP_OK) return s;
   }
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, st, (const DevPlan*)nullptr, (const FoldTask*)nullptr, 0,
-                     (void* const*)nullptr, (unsigned char* const*)nullptr);
+                     (void* const*)nullptr, (unsigned char* const*)nullptr, (unsigned int*)nullptr, 0);
   hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, (unsigned int*)nullptr, 0);
   if (hipGetLastError() != hipSuccess) return fail(HP_EDEVICE, "warm-up launch failed");
   return HP_OK;
@@ -266,15 +269,16 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
     members[g].push_back(i);
   }
   // device memory: plans, pointer tables, then one arena for tasks, counters and workspaces
-  size_t arena_bytes = 0;
+  // the task counters of every group sit together at the start (zero after the
+  // upload; each run leaves them at zero again), then each group's task list
+  size_t arena_bytes = align_up(keys.size() * kCtrWords * sizeof(unsigned int), 256);
   std::vector<size_t> task_off(keys.size()), ctr_off(keys.size());
   std::vector<long long> ntask(keys.size(), 0);
   for (size_t g = 0; g < keys.size(); ++g) {
     for (int64_t i : members[g]) ntask[g] += b->plans[(size_t)i].grid;
+    ctr_off[g] = g * kCtrWords * sizeof(unsigned int);
     task_off[g] = arena_bytes;
     arena_bytes = align_up(arena_bytes + (size_t)ntask[g] * sizeof(int2), 256);
-    ctr_off[g] = arena_bytes;
-    arena_bytes = align_up(arena_bytes + kCtrWords * sizeof(unsigned int), 256);
     if (ntask[g] > 0x7fffffffLL) {
       batch_free(b);
       return fail(HP_ETOOBIG, "batch group has %lld tasks, more than 2^31 - 1", ntask[g]);
@@ -409,11 +413,15 @@ static hp_status launch_groups(hp_batch_s* b, hipStream_t st) {
     A.ins = b->d_in;
     A.outs = b->d_out;
     A.wss = b->d_ws;
-    hp_status s = hp::launch_clear(A.ctr, hp::kCtrWords, st);
+    // With fold tasks, the fold kernel that ends the run clears the counters for
+    // the next one; without, each group clears its own before it starts.
+    hp_status s = b->n_fold > 0 ? HP_OK : hp::launch_clear(A.ctr, hp::kCtrWords, st);
     if (s == HP_OK) s = hp::launch_batch(G.family, G.chunk, A, G.grid, hp::kBatchGroupWaves, G.lds, st);
     if (s != HP_OK) return s;
   }
-  return hp::launch_fold(b->d_plans, b->d_fold, b->n_fold, b->d_out, b->d_ws, st);
+  if (b->n_fold <= 0) return HP_OK;
+  return hp::launch_fold(b->d_plans, b->d_fold, b->n_fold, b->d_out, b->d_ws, st,
+                         reinterpret_cast<unsigned int*>(b->arena), (int)(b->groups.size() * hp::kCtrWords));
 }
 
 static hp_status capture(hp_batch_s* b, bool each, hipGraph_t* graph, hipGraphExec_t* exec);

@@ -153,9 +153,11 @@ inline void fold_tasks_of(const DevPlan& P, int nest, std::vector<FoldTask>& v) 
   }
 }
 
-// Fold the grid-split outputs: n fold tasks over a pointer table of nests.
+// Fold the grid-split outputs: n fold tasks over a pointer table of nests.  When
+// ctr is given, the kernel also sets its n_ctr words to zero (the task counters of
+// the persistent launches that ran before it, ready for the next run).
 hp_status launch_fold(const DevPlan* plans, const FoldTask* tasks, int n, void* const* outs,
-                      unsigned char* const* wss, hipStream_t st);
+                      unsigned char* const* wss, hipStream_t st, unsigned int* ctr = nullptr, int n_ctr = 0);
 // The same for a single plan.
 hp_status launch_fold_one(const DevPlan* plan, const FoldTask* tasks, int n, void* out, const unsigned char* ws,
                           hipStream_t st);

@@ -110,12 +110,55 @@ def test_batch_mixed_families():
         b.set_io(ins, outs)
         st = b.stats()
         assert st["launches"] >= 3
-        b.run()
-        torch.cuda.synchronize()
-        for i, (ext, ops, dt) in enumerate(nests):
-            n = int(np.prod(ext))
-            x = (hi[offi[i]:offi[i] + n] if dt == 0 else hf[offf[i]:offf[i] + n]).reshape(ext)
-            assert_match(outs[i].cpu().numpy(), np.ascontiguousarray(x), ext, ops, what=f"mixed nest {i}")
+        # several runs in a row: each must find its task counters cleared by the last
+        for r in range(3):
+            for t in outs:
+                t.zero_()
+            torch.cuda.synchronize()
+            b.run()
+            torch.cuda.synchronize()
+            for i, (ext, ops, dt) in enumerate(nests):
+                n = int(np.prod(ext))
+                x = (hi[offi[i]:offi[i] + n] if dt == 0 else hf[offf[i]:offf[i] + n]).reshape(ext)
+                assert_match(outs[i].cpu().numpy(), np.ascontiguousarray(x), ext, ops, what=f"run {r} mixed nest {i}")
+
+
+def test_batch_mixed_families_graph_replays():
+    """The multi-launch batch replayed from a graph, with and without grid-split
+    nests (the fold kernel, when there is one, clears the task counters for the
+    next replay; otherwise each launch clears its own)."""
+    import paper_2309_01906_amd as hp
+    for split in (True, False):
+        nests = [((7, 300), ("NONE", "SUM"), 0), ((3, 64, 64), ("NONE", "MAX", "ARGMIN"), 0),
+                 ((5, 4096), ("NONE", "SUM"), 1), ((4, 5), ("NONE", "SUM"), 1)]
+        if split:
+            nests += [((1, 1 << 20), ("NONE", "SUM"), 1), ((1, 1 << 20), ("NONE", "ARGMAX"), 0)]
+        hi, offi = packed(nests, 98, "i32")
+        hf, offf = packed(nests, 99, "f32")
+        di, df = to_device(hi), to_device(hf)
+        say("case batch mixed graph", "split" if split else "no split")
+        with hp.Batch(nests, hp.BATCH_GRAPH) as b:
+            ins, outs = [], []
+            for i, (ext, ops, dt) in enumerate(nests):
+                n = int(np.prod(ext))
+                ins.append(di[offi[i]:offi[i] + n] if dt == 0 else df[offf[i]:offf[i] + n])
+                inf = b.info(i)
+                outs.append(torch.zeros(inf["n_out"], dtype=hp.torch_out_dtype(inf["out_dtype"]), device="cuda"))
+            b.set_io(ins, outs)
+            assert b.stats()["launches"] >= 2
+            assert any(b.info(i)["gsplit"] > 1 for i in range(len(nests))) == split
+            for r in range(4):
+                for t in outs:
+                    t.zero_()
+                torch.cuda.synchronize()
+                b.run()
+                torch.cuda.synchronize()
+                for i, (ext, ops, dt) in enumerate(nests):
+                    n = int(np.prod(ext))
+                    x = (hi[offi[i]:offi[i] + n] if dt == 0 else hf[offf[i]:offf[i] + n]).reshape(ext)
+                    assert_match(outs[i].cpu().numpy(), np.ascontiguousarray(x), ext, ops,
+                                 what=f"replay {r} nest {i}")
+                torch.sum(di[:1024].float()).item()  # eager work between replays
 
 
 def test_tuner_then_batch():
