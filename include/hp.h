@@ -78,8 +78,15 @@ typedef enum hp_op {
 } hp_op;
 
 /* Scope bits of a level map.  A level may use several adjacent scopes (a
- * collapse, section 3.1); L adds nothing but allows serial strips. */
-enum { HP_SCOPE_G = 1, HP_SCOPE_W = 2, HP_SCOPE_V = 4, HP_SCOPE_L = 8 };
+ * collapse, section 3.1); L adds nothing but allows serial strips.
+ * HP_SCOPE_X names the chip's 8 XCDs, a hardware level between the grid and the
+ * workgroup (section 3.2's levels by property: an XCD shares one L2).  A level on
+ * X gets 8 grid units, one per XCD: its unit index is the XCD the workgroup runs
+ * on.  It counts as G for every other rule (X together with W is X+W), only the
+ * first level that uses the grid may use it, at most one level does, and the plan
+ * needs a grid of at least 16 workgroups that is a multiple of 8 with XCD
+ * numbering on (no HP_FLAG_NO_XCD): else HP_EINVAL / HP_EUNSUPPORTED. */
+enum { HP_SCOPE_G = 1, HP_SCOPE_W = 2, HP_SCOPE_V = 4, HP_SCOPE_L = 8, HP_SCOPE_X = 16 };
 /* Axis index into hp_level_map.units[level][axis]. */
 enum { HP_AXIS_G = 0, HP_AXIS_W = 1, HP_AXIS_V = 2 };
 

@@ -23,7 +23,7 @@ NONE, SUM, MIN, MAX, ARGMIN, ARGMAX, PROD = 0, 1, 2, 3, 4, 5, 6
 I32, F32, BF16, I64, F64, AFFINE64, MAT2X2_64 = 0, 1, 2, 3, 4, 5, 6
 # uint64 words per element of the ordered-product types (tensors hold them as int64)
 WIDTH = {AFFINE64: 2, MAT2X2_64: 4}
-SCOPE = {"G": 1, "W": 2, "V": 4, "L": 8}
+SCOPE = {"G": 1, "W": 2, "V": 4, "L": 8, "X": 16}
 AXIS = {"G": 0, "W": 1, "V": 2}
 FLAG_OUT_F32, FLAG_SCALAR, FLAG_NO_XCD, FLAG_GENERIC = 0x1, 0x2, 0x4, 0x10
 OP_NAMES = {"NONE": NONE, "SUM": SUM, "MIN": MIN, "MAX": MAX, "ARGMIN": ARGMIN, "ARGMAX": ARGMAX, "PROD": PROD}
@@ -153,7 +153,10 @@ def _info_dict(inf: PlanInfo) -> dict:
         "in_elems": inf.in_elems, "in_bytes": inf.in_bytes, "grid": inf.grid, "waves": inf.waves,
         "chunk": inf.chunk, "gsplit": inf.gsplit, "workspace_bytes": inf.workspace_bytes,
         "lds_bytes": inf.lds_bytes, "nseg": inf.nseg, "kernel": inf.kernel, "kernel_name": kernel_name(inf),
-        "map": ["".join(names[b] for b in range(4) if inf.scopes[i] >> b & 1) for i in range(d)],
+        # a level on X reports "X" in place of the G it lowers to
+        "map": [("X" if inf.scopes[i] & 16 else "") +
+                "".join(names[b] for b in range(4) if inf.scopes[i] >> b & 1 and not (b == 0 and inf.scopes[i] & 16))
+                for i in range(d)],
         "units": [tuple(inf.units[i][a] for a in range(3)) for i in range(d)],
         "strips": [inf.strips[i] for i in range(d)],
     }

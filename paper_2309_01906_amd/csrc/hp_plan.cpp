@@ -305,6 +305,23 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
   } else {
     auto_map(n, p, chunk_last, &m, force_nw);
   }
+  // ---- the XCD scope: 8 grid units on the outermost grid digit, which the
+  // XCD-aware workgroup numbering makes the XCD index
+  int xlevel = -1;
+  for (int l = 0; l < d; ++l) {
+    if (!(m.scopes[l] & HP_SCOPE_X)) continue;
+    if (xlevel >= 0) return fail(HP_EINVAL, "levels %d and %d both use the XCD scope X", xlevel, l);
+    if (m.scopes[l] & HP_SCOPE_G) return fail(HP_EINVAL, "level %d uses both X and G", l);
+    for (int k = 0; k < l; ++k)
+      if (m.scopes[k] & (HP_SCOPE_G | HP_SCOPE_X))
+        return fail(HP_EINVAL, "X at level %d: level %d outside it already uses the grid", l, k);
+    if (m.units[l][HP_AXIS_G] && m.units[l][HP_AXIS_G] != 8)
+      return fail(HP_EINVAL, "X at level %d has 8 units, not %u", l, m.units[l][HP_AXIS_G]);
+    if (flags & HP_FLAG_NO_XCD) return fail(HP_EINVAL, "X at level %d with HP_FLAG_NO_XCD", l);
+    m.scopes[l] = (m.scopes[l] & ~(uint32_t)HP_SCOPE_X) | HP_SCOPE_G;
+    m.units[l][HP_AXIS_G] = 8;
+    xlevel = l;
+  }
   // ---- validate the map
   for (int l = 0; l < d; ++l) {
     const uint32_t s = m.scopes[l];
@@ -580,6 +597,9 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     if (dp.lv[l].strips > 0x7FFFFFFFll)
       return fail(HP_EUNSUPPORTED, "level %d needs more than 2^31 strips; give it more units", l);
   dp.xcd = (!(flags & HP_FLAG_NO_XCD) && dp.grid % 8 == 0 && dp.grid >= 16) ? 1 : 0;
+  if (xlevel >= 0 && (!dp.xcd || (int64_t)dp.lv[xlevel].gdiv * 8 != dp.grid))
+    return fail(HP_EUNSUPPORTED, "X at level %d needs a grid of at least 16 workgroups, a multiple of 8 (it has %lld)",
+                xlevel, (long long)dp.grid);
   // ---- output kind
   if (is_float) {
     dp.out_kind = (flags & HP_FLAG_OUT_F32) ? OUT_F32 : OUT_F64;
@@ -629,7 +649,7 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     I.lds_bytes = (slots > gcomb ? slots : gcomb) + 16;
   }
   for (int l = 0; l < d; ++l) {
-    I.scopes[l] = m.scopes[l];
+    I.scopes[l] = m.scopes[l] | (l == xlevel ? (uint32_t)HP_SCOPE_X : 0u);
     I.units[l][HP_AXIS_G] = dp.lv[l].gf;
     I.units[l][HP_AXIS_W] = (uint32_t)dp.lv[l].wf;
     I.units[l][HP_AXIS_V] = (uint32_t)dp.lv[l].vf;

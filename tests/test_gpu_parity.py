@@ -248,6 +248,35 @@ def test_arg_rows_of_extreme_values(fill):
         assert_match(got, x, ext, ops, what=f"extreme {fill} {ext} {ops}")
 
 
+def test_xcd_scope_maps():
+    """Levels placed on the XCD scope give the oracle's results (bit-exact for
+    integers, and the same bits as the automatic map), for an output level and
+    for a reducing level on X."""
+    import paper_2309_01906_amd as hp
+    c3 = workloads.C3
+    x = workloads.c3_input()
+    dev = to_device(x)
+    ops = c3.ops
+    auto, _ = gpu_reduce(x, c3.extents, ops, dev=dev)
+    m = ["X", ("GW", {"G": 16, "W": 8}), ("V", {"V": 16}), ("V", {"V": 4})]
+    got, info = gpu_reduce(x, c3.extents, ops, m, dev=dev)
+    say("case xcd c3", info["map"], info["grid"])
+    assert info["map"][0] == "X"
+    np.testing.assert_array_equal(got, auto)
+    assert_match(got, x, c3.extents, ops, what="X map c3")
+    for ext, ops, m in [((64, 64, 256), ("SUM", "SUM", "SUM"), ["X", ("GW", {"G": 4, "W": 4}), "V"]),
+                        ((40, 64, 256), ("NONE", "SUM", "SUM"), [("XW", {"W": 2}), ("W", {"W": 4}), "V"]),
+                        ((3, 1000, 100), ("NONE", "SUM", "SUM"), ["X", ("GW", {"G": 2, "W": 2}), "V"])]:
+        xf = workloads.normal_f32(78, ext)
+        try:
+            got, info = gpu_reduce(xf, ext, ops, m)
+        except hp.HPError as e:
+            assert e.status_name == "HP_EUNSUPPORTED", (ext, m, str(e))
+            continue
+        say("case xcd float", ext, info["map"], info["grid"])
+        assert_match(got, xf, ext, ops, what=f"X map {ext}")
+
+
 def test_flags_scalar_out_f32_noxcd_generic():
     import paper_2309_01906_amd as hp
     x = workloads.normal_f32(73, (256, 4096))

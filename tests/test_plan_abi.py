@@ -187,3 +187,24 @@ def test_stencil_plan_rejections():
     assert L.hp_stencil_run(s._h, None, None, None) == 1          # null arrays
     assert L.hp_stencil_run(s._h, 4096, 4096 + 64, None) == 1     # overlapping arrays
     s.close()
+
+
+def test_xcd_scope_planning():
+    """X: 8 grid units on the outermost grid digit (the XCD index under XCD-aware
+    numbering), G for every other rule; the rejections name the broken rule."""
+    c3 = ((64, 128, 64, 64), (hp.NONE, hp.SUM, hp.MAX, hp.ARGMIN), hp.I32)
+    i = hp.inspect(*c3, ["X", ("GW", {"G": 16, "W": 8}), ("V", {"V": 16}), ("V", {"V": 4})])
+    assert i["map"] == ["X", "GW", "V", "V"]
+    assert i["units"][0][0] == 8 and i["grid"] == 8 * 16 and i["gsplit"] == 16
+    i = hp.inspect((64, 64, 256), (hp.SUM, hp.SUM, hp.SUM), hp.F32, ["X", ("GW", {"G": 4, "W": 4}), "V"])
+    assert i["map"] == ["X", "GW", "V"] and i["grid"] == 32 and i["gsplit"] == 32
+    bad = [(c3, ["G", "X", "V", "L"], 0, "HP_EINVAL", "already uses the grid"),
+           (c3, ["X", "GW", "V", "V"], hp.FLAG_NO_XCD, "HP_EINVAL", "NO_XCD"),
+           (c3, ["X", "X", "V", "V"], 0, "HP_EINVAL", "both use"),
+           (c3, [("X", {"G": 4}), "GW", "V", "V"], 0, "HP_EINVAL", "8 units"),
+           (c3, ["XG", "W", "V", "V"], 0, "HP_EINVAL", "both X and G"),
+           (((4, 64), (hp.NONE, hp.SUM), hp.I32), ["X", "V"], 0, "HP_EUNSUPPORTED", "at least 16")]
+    for (ext, ops, dt), m, fl, status, words in bad:
+        with pytest.raises(hp.HPError) as e:
+            hp.inspect(ext, ops, dt, m, fl)
+        assert e.value.status_name == status and words in str(e.value), (m, str(e.value))
