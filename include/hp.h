@@ -274,7 +274,11 @@ hp_status hp_tune_cache_size(int64_t* n);
  * slots is free and either max_batch requests wait, the oldest has waited
  * window_us, or the device is idle.  Batches of different slots overlap on the
  * device.  Request state (plans, task lists, fold tasks, partials) lives in the
- * slot's device arena.  Each request keeps the plan it would get alone, so its
+ * slot's device arena; a request joins a batch only while its share of that arena
+ * still fits (else it waits for the next batch, under the same bounded bypass), so
+ * no request fails because of what it was packed with.  If a launch fails after
+ * some of its work was enqueued, the slot stays busy until its stream has drained,
+ * and only then are its requests failed (HP_EDEVICE).  Each request keeps the plan it would get alone, so its
  * result does not depend on the batch it ran in.  Payloads are not copied: d_in
  * and d_out must stay valid until the request completes.
  */
@@ -290,7 +294,9 @@ typedef struct hp_server_cfg {
   int32_t window_us;              /* how long a partial batch may wait while the device is busy */
   int32_t queue_cap;              /* pending requests before hp_submit returns HP_EAGAIN */
   uint32_t flags;                 /* HP_FLAG_OUT_F32, HP_SERVER_FAKE_DEVICE */
-  int32_t fail_every_nth_batch;   /* test hook: every n-th batch fails without running (0: never) */
+  int32_t fail_every_nth_batch;   /* test hook: every n-th batch fails (0: never) ... */
+  int32_t fail_step;              /* ... before its device step fail_step: 0 the descriptor upload, then one
+                                     step per persistent launch and the fold launch (clamped to the last) */
 } hp_server_cfg;
 
 typedef struct hp_req_info {
@@ -319,7 +325,8 @@ hp_status hp_server_create(const hp_server_cfg* cfg, hp_server_t* out);
 /* Submit one request; t_arrival_us < 0 stamps the current server time (an
  * open-loop client passes its scheduled arrival time instead).  The nest is
  * planned here (errors as hp_plan_inspect).  HP_ETOOBIG if it alone exceeds the
- * budget, HP_EAGAIN if the queue is full, HP_ESTATE after shutdown began. */
+ * budget or its descriptors and workspace alone exceed slot_bytes, HP_EAGAIN if the
+ * queue is full, HP_ESTATE after shutdown began. */
 hp_status hp_submit(hp_server_t s, const hp_nest* nest, const void* d_in, void* d_out, double t_arrival_us,
                     uint64_t* ticket);
 
@@ -349,9 +356,9 @@ hp_status hp_server_replay(hp_server_t s, int64_t n, const hp_nest* nests, const
 hp_status hp_server_destroy(hp_server_t s);
 
 /* ---------------------------------------------------------------------------
- * Stencils (the paper's second class of multi-level algorithms, section 4: a
+ * Stencils (the paper's second class of multi-level algorithms, section 2: a
  * region whose input fits a level's local memory, repeated on every level with
- * local memory; section 6: array sections that overlap by a ghost surface).
+ * local memory; section 4: array sections that overlap by a ghost surface).
  * `steps` five-point Jacobi sweeps of a rows x cols row-major float array,
  *   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1]))
  * for 1 <= i <= rows-2, 1 <= j <= cols-2 (fp32, in exactly this order, no fused

@@ -466,7 +466,7 @@ SERVER_FAKE_DEVICE = 0x1000
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("slot_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("window_us", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("fail_every_nth_batch", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("fail_every_nth_batch", ctypes.c_int32), ("fail_step", ctypes.c_int32)]
 
 
 class ReqInfo(ctypes.Structure):
@@ -516,10 +516,10 @@ class Server:
     """hp_server_*: continuous batching of nest-reduction requests."""
 
     def __init__(self, hbm_budget=64 << 30, slot_bytes=64 << 20, streams=4, max_batch=1024, window_us=30,
-                 queue_cap=1 << 20, flags=0, fail_every_nth_batch=0):
+                 queue_cap=1 << 20, flags=0, fail_every_nth_batch=0, fail_step=0):
         _server_sigs()
         cfg = ServerCfg(hbm_budget, slot_bytes, streams, max_batch, window_us, queue_cap, flags,
-                        fail_every_nth_batch)
+                        fail_every_nth_batch, fail_step)
         self._h = ctypes.c_void_p()
         check(lib().hp_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
 

@@ -9,8 +9,11 @@ namespace hp {
 // counters -- a dynamic schedule on the grid level.  The tasks are dealt, largest
 // first, into kQueues queues with one counter each; workgroup b takes from queue
 // b % kQueues, which is the XCD the hardware places it on, so the counters are
-// contended by one XCD each instead of the whole chip.  The counters are cleared by
-// a separate small kernel before every run, so a run can be replayed from a graph.
+// contended by one XCD each instead of the whole chip.  Every run leaves the
+// counters at zero for the next one, so a run can be replayed from a graph: the
+// fold kernel that ends a run with grid-split nests clears them (the persistent
+// launches before it on the stream have finished), and a batch without fold tasks
+// clears them with a small kernel before each persistent launch.
 constexpr int kQueues = 8;
 constexpr int kCtrStride = 64;  // counters 256 bytes apart
 

@@ -140,6 +140,12 @@ __device__ __forceinline__ void fold_task(const DevPlan& P, const FoldTask& t, v
   else store_int(P, out, o, fold_int_nested<kMaxDepth>(P, part));
 }
 
+// Host side: how many fold tasks fold_tasks_of appends for plan P.
+inline long long fold_task_count(const DevPlan& P) {
+  if (P.gmode == GCOMB_NONE || P.gsplit <= 1) return 0;
+  return fold_on_lane(P) ? (P.n_out + kWave - 1) / kWave : P.n_out;
+}
+
 // Host side: the fold tasks of one plan (appended to v).
 inline void fold_tasks_of(const DevPlan& P, int nest, std::vector<FoldTask>& v) {
   if (P.gmode == GCOMB_NONE || P.gsplit <= 1) return;

@@ -2,8 +2,9 @@
 //
 // Follows the paper's section 3: explicit level selection with collapse (3.1),
 // selection by property for the automatic map (3.2: reductions need a shuffle at
-// the wavefront, a barrier and local memory at the workgroup, and an atomic at the
-// grid, which has no barrier), the reserve rule that makes maps monotone (3.3),
+// the wavefront, a barrier and local memory at the workgroup; the grid has no
+// barrier, so its partials are folded by a second kernel after the launch), the
+// reserve rule that makes maps monotone (3.3),
 // strip-mining every level once all units are started (3.4, SPMD mode), static /
 // masked schedules (3.5) and splitting a hardware level between nested loops (3.8).
 #include <cstdarg>
@@ -597,8 +598,9 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     if (dp.lv[l].strips > 0x7FFFFFFFll)
       return fail(HP_EUNSUPPORTED, "level %d needs more than 2^31 strips; give it more units", l);
   dp.xcd = (!(flags & HP_FLAG_NO_XCD) && dp.grid % 8 == 0 && dp.grid >= 16) ? 1 : 0;
-  if (xlevel >= 0 && (!dp.xcd || (int64_t)dp.lv[xlevel].gdiv * 8 != dp.grid))
-    return fail(HP_EUNSUPPORTED, "X at level %d needs a grid of at least 16 workgroups, a multiple of 8 (it has %lld)",
+  // a grid of exactly 8 needs no renumbering: workgroup b already runs on XCD b
+  if (xlevel >= 0 && (!(dp.xcd || dp.grid == 8) || (int64_t)dp.lv[xlevel].gdiv * 8 != dp.grid))
+    return fail(HP_EUNSUPPORTED, "X at level %d needs a grid that is 8 or a multiple of 8 of at least 16 (it has %lld)",
                 xlevel, (long long)dp.grid);
   // ---- output kind
   if (is_float) {

@@ -44,7 +44,101 @@ struct Request {
   size_t bytes;  // budget charge
   hp_req_info info;
   int bypassed;
+  // what the request adds to a slot arena (see Tally)
+  std::pair<int, int> key;  // kernel family and chunk: one persistent launch per key
+  long long ntask;          // workgroup tasks
+  long long nfold;          // fold tasks
+  size_t ws;                // grid-combine workspace, 256-byte aligned
 };
+
+size_t A256(size_t x) { return align_up(x, 256); }
+
+// Bytes of slot arena a batch needs: plans, the pointer tables, per kernel family
+// its task list and queue counters, the fold tasks and the workspaces, each region
+// 256-byte aligned.  layout_batch lays the regions out in this order; Tally keeps
+// the same sum up to date while a batch is packed, one request at a time, so a
+// batch never outgrows its slot.
+struct Tally {
+  int64_t n = 0;
+  long long nfold = 0;
+  size_t ws = 0;
+  std::vector<std::pair<int, int>> keys;
+  std::vector<long long> ntask;
+
+  size_t total() const {
+    size_t t = A256(sizeof(hp::DevPlan) * (size_t)n) + A256(3 * sizeof(void*) * (size_t)n);
+    for (long long k : ntask) t += A256((size_t)k * sizeof(int2)) + A256(hp::kCtrWords * sizeof(unsigned int));
+    return t + A256((size_t)nfold * sizeof(hp::FoldTask)) + ws;
+  }
+  void add(const Request& r) {
+    ++n;
+    nfold += r.nfold;
+    ws += r.ws;
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != r.key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(r.key);
+      ntask.push_back(0);
+    }
+    ntask[g] += r.ntask;
+  }
+  size_t total_with(const Request& r) const {
+    Tally t = *this;
+    t.add(r);
+    return t.total();
+  }
+};
+
+struct Layout {
+  size_t plans_off = 0, ptr_off = 0, fold_off = 0, ws_begin = 0, total = 0;
+  std::vector<std::pair<int, int>> keys;
+  std::vector<std::vector<int64_t>> members;
+  std::vector<size_t> task_off, ctr_off;
+  std::vector<long long> ntask;
+  std::vector<hp::FoldTask> folds;
+  std::vector<size_t> ws_off;
+};
+
+void layout_batch(const std::vector<Request*>& rs, Layout& Lo) {
+  using namespace hp;
+  const int64_t n = (int64_t)rs.size();
+  size_t off = 0;
+  Lo.plans_off = off;
+  off = align_up(off + sizeof(DevPlan) * (size_t)n, 256);
+  Lo.ptr_off = off;
+  off = align_up(off + 3 * sizeof(void*) * (size_t)n, 256);
+  for (int64_t i = 0; i < n; ++i) {
+    size_t g = 0;
+    while (g < Lo.keys.size() && Lo.keys[g] != rs[(size_t)i]->key) ++g;
+    if (g == Lo.keys.size()) {
+      Lo.keys.push_back(rs[(size_t)i]->key);
+      Lo.members.emplace_back();
+    }
+    Lo.members[g].push_back(i);
+  }
+  Lo.task_off.resize(Lo.keys.size());
+  Lo.ctr_off.resize(Lo.keys.size());
+  Lo.ntask.assign(Lo.keys.size(), 0);
+  for (size_t g = 0; g < Lo.keys.size(); ++g) {
+    for (int64_t i : Lo.members[g]) Lo.ntask[g] += rs[(size_t)i]->ntask;
+    Lo.task_off[g] = off;
+    off = align_up(off + (size_t)Lo.ntask[g] * sizeof(int2), 256);
+    Lo.ctr_off[g] = off;
+    off = align_up(off + kCtrWords * sizeof(unsigned int), 256);
+  }
+  for (int64_t i = 0; i < n; ++i) fold_tasks_of(rs[(size_t)i]->L.dp, (int)i, Lo.folds);
+  Lo.fold_off = off;
+  off = align_up(off + Lo.folds.size() * sizeof(FoldTask), 256);
+  Lo.ws_begin = off;
+  Lo.ws_off.assign((size_t)n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (rs[(size_t)i]->ws) {
+      Lo.ws_off[(size_t)i] = off;
+      off += rs[(size_t)i]->ws;
+    }
+  }
+  Lo.total = off;
+}
 
 struct Slot {
   hipStream_t st = nullptr;
@@ -58,6 +152,9 @@ struct Slot {
   double t_launch = 0;
   double fake_done = 0;  // fake executor: completion time
   int64_t batch_id = 0;
+  // a launch failed after work was enqueued: the slot stays busy until its stream
+  // has drained (the event of the last enqueued step), then its requests fail with err
+  int32_t err = HP_OK;
 };
 
 }  // namespace
@@ -97,118 +194,127 @@ namespace {
 int occ_key(int fam, int chunk) { return fam * 16 + chunk; }
 
 // Lay out a batch in the slot's staging buffer, copy it to the device arena and
-// launch one persistent kernel per (family, chunk) group.
-hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs) {
+// launch one persistent kernel per (family, chunk) group, then the fold kernel.
+// These device steps go onto the slot's stream in order.  On failure, *drain says
+// whether some of them were already enqueued: then the slot must stay busy until
+// its stream has finished with the staging buffer and the arena.  The fake executor
+// (host-only tests) runs the same layout and steps without touching a device.
+hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs, bool* drain) {
   using namespace hp;
+  *drain = false;
   const int64_t n = (int64_t)rs.size();
-  size_t off = 0;
-  const size_t plans_off = off;
-  off = align_up(off + sizeof(DevPlan) * (size_t)n, 256);
-  const size_t ptr_off = off;
-  off = align_up(off + 3 * sizeof(void*) * (size_t)n, 256);
-  // groups
-  std::vector<std::pair<int, int>> keys;
-  std::vector<std::vector<int64_t>> members;
-  for (int64_t i = 0; i < n; ++i) {
-    std::pair<int, int> k(family_of(rs[(size_t)i]->L.dp), rs[(size_t)i]->L.dp.chunk);
-    size_t g = 0;
-    while (g < keys.size() && keys[g] != k) ++g;
-    if (g == keys.size()) {
-      keys.push_back(k);
-      members.emplace_back();
+  Layout Lo;
+  layout_batch(rs, Lo);
+  if (Lo.total > slot.cap)
+    return fail(HP_ETOOBIG, "batch needs %zu bytes of slot arena, capacity %zu", Lo.total, slot.cap);
+  const size_t lds = (size_t)kBatchGroupWaves * kWaveLdsBytes;
+  const int n_steps = 1 + (int)Lo.keys.size() + (Lo.folds.empty() ? 0 : 1);
+  // test hook: this batch fails before device step fail_step (0: before the upload)
+  int fail_at = -1;
+  if (S->fail_every > 0 && slot.batch_id % S->fail_every == 0)
+    fail_at = S->cfg.fail_step < n_steps ? S->cfg.fail_step : n_steps;
+  double work = 0;  // fake executor: bytes the enqueued steps read
+  auto hook = [&](int step) -> hp_status {
+    if (step != fail_at) return HP_OK;
+    *drain = step > 0;
+    return fail(HP_EDEVICE, "injected failure before device step %d", step);
+  };
+  if (S->fake) {
+    for (int step = 0; step <= n_steps; ++step) {
+      hp_status s = hook(step);
+      if (s != HP_OK) {
+        slot.fake_done = S->now() + 5.0 + work / 4.0e3;
+        return s;
+      }
+      if (step > 0 && step <= (int)Lo.keys.size())
+        for (int64_t i : Lo.members[(size_t)step - 1]) work += (double)rs[(size_t)i]->L.info.in_bytes;
     }
-    members[g].push_back(i);
+    slot.fake_done = S->now() + 5.0 + work / 4.0e3;  // a 4 GB/s pretend device
+    return HP_OK;
   }
-  std::vector<size_t> task_off(keys.size()), ctr_off(keys.size());
-  std::vector<long long> ntask(keys.size(), 0);
-  for (size_t g = 0; g < keys.size(); ++g) {
-    for (int64_t i : members[g]) ntask[g] += rs[(size_t)i]->L.dp.grid;
-    task_off[g] = off;
-    off = align_up(off + (size_t)ntask[g] * sizeof(int2), 256);
-    ctr_off[g] = off;
-    off = align_up(off + kCtrWords * sizeof(unsigned int), 256);
-  }
-  std::vector<FoldTask> folds;
-  for (int64_t i = 0; i < n; ++i) fold_tasks_of(rs[(size_t)i]->L.dp, (int)i, folds);
-  const size_t fold_off = off;
-  off = align_up(off + folds.size() * sizeof(FoldTask), 256);
-  const size_t ws_begin = off;
-  std::vector<size_t> ws_off((size_t)n, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    const size_t wb = rs[(size_t)i]->L.info.workspace_bytes;
-    if (wb) {
-      ws_off[(size_t)i] = off;
-      off = align_up(off + wb, 256);
-    }
-  }
-  if (off > slot.cap) return fail(HP_ETOOBIG, "batch needs %zu bytes of slot arena, capacity %zu", off, slot.cap);
   unsigned char* h = slot.h_stage;
   unsigned char* d = slot.d_arena;
-  DevPlan* hp_ = reinterpret_cast<DevPlan*>(h + plans_off);
-  const void** hin = reinterpret_cast<const void**>(h + ptr_off);
-  void** hout = reinterpret_cast<void**>(h + ptr_off) + n;
-  unsigned char** hws = reinterpret_cast<unsigned char**>(h + ptr_off) + 2 * n;
+  DevPlan* hp_ = reinterpret_cast<DevPlan*>(h + Lo.plans_off);
+  const void** hin = reinterpret_cast<const void**>(h + Lo.ptr_off);
+  void** hout = reinterpret_cast<void**>(h + Lo.ptr_off) + n;
+  unsigned char** hws = reinterpret_cast<unsigned char**>(h + Lo.ptr_off) + 2 * n;
   for (int64_t i = 0; i < n; ++i) {
     hp_[i] = rs[(size_t)i]->L.dp;
     hin[i] = rs[(size_t)i]->in;
     hout[i] = rs[(size_t)i]->out;
-    hws[i] = ws_off[(size_t)i] ? d + ws_off[(size_t)i] : nullptr;
+    hws[i] = Lo.ws_off[(size_t)i] ? d + Lo.ws_off[(size_t)i] : nullptr;
   }
-  const size_t lds = (size_t)kBatchGroupWaves * kWaveLdsBytes;
-  std::vector<BatchArgs> args(keys.size());
-  std::vector<int> grid(keys.size());
-  for (size_t g = 0; g < keys.size(); ++g) {
-    std::vector<int64_t>& mem = members[g];
+  std::vector<BatchArgs> args(Lo.keys.size());
+  std::vector<int> grid(Lo.keys.size());
+  for (size_t g = 0; g < Lo.keys.size(); ++g) {
+    std::vector<int64_t>& mem = Lo.members[g];
     std::stable_sort(mem.begin(), mem.end(), [&](int64_t a, int64_t c) {
       const double wa = (double)rs[(size_t)a]->L.info.in_bytes / (double)rs[(size_t)a]->L.dp.grid;
       const double wc = (double)rs[(size_t)c]->L.info.in_bytes / (double)rs[(size_t)c]->L.dp.grid;
       return wa > wc;
     });
-    std::vector<int2> ordered((size_t)ntask[g]);
+    std::vector<int2> ordered((size_t)Lo.ntask[g]);
     long long k = 0;
     for (int64_t i : mem)
       for (long long w = 0; w < rs[(size_t)i]->L.dp.grid; ++w) ordered[(size_t)k++] = make_int2((int)i, (int)w);
-    const int key = occ_key(keys[g].first, keys[g].second);
+    const int key = occ_key(Lo.keys[g].first, Lo.keys[g].second);
     auto it = S->occ.find(key);
     int o;
     if (it == S->occ.end()) {
-      o = batch_occupancy(keys[g].first, keys[g].second, kBatchGroupWaves, lds);
+      o = batch_occupancy(Lo.keys[g].first, Lo.keys[g].second, kBatchGroupWaves, lds);
       if (o < 1) o = 1;
       S->occ[key] = o;
     } else {
       o = it->second;
     }
     long long gr = (long long)S->cus * o;
-    const long long need = (ntask[g] + kBatchGroupWaves - 1) / kBatchGroupWaves;
+    const long long need = (Lo.ntask[g] + kBatchGroupWaves - 1) / kBatchGroupWaves;
     if (gr > need) gr = need;
     grid[g] = (int)gr;
-    deal_tasks(ordered.data(), (int)ntask[g], grid[g], reinterpret_cast<int2*>(h + task_off[g]), &args[g]);
-    memset(h + ctr_off[g], 0, kCtrWords * sizeof(unsigned int));
+    deal_tasks(ordered.data(), (int)Lo.ntask[g], grid[g], reinterpret_cast<int2*>(h + Lo.task_off[g]), &args[g]);
+    memset(h + Lo.ctr_off[g], 0, kCtrWords * sizeof(unsigned int));
   }
-  if (!folds.empty()) memcpy(h + fold_off, folds.data(), folds.size() * sizeof(FoldTask));
-  // upload the descriptors; the workspaces need no clearing (every partial is written
-  // before the fold kernel reads it)
-  if (hipMemcpyAsync(d, h, ws_begin, hipMemcpyHostToDevice, slot.st) != hipSuccess)
+  if (!Lo.folds.empty()) memcpy(h + Lo.fold_off, Lo.folds.data(), Lo.folds.size() * sizeof(FoldTask));
+  // step 0: upload the descriptors; the workspaces need no clearing (every partial
+  // is written before the fold kernel reads it)
+  hp_status s = hook(0);
+  if (s != HP_OK) return s;
+  if (hipMemcpyAsync(d, h, Lo.ws_begin, hipMemcpyHostToDevice, slot.st) != hipSuccess)
     return fail(HP_EDEVICE, "batch upload failed");
-  for (size_t g = 0; g < keys.size(); ++g) {
+  int step = 1;
+  // after the first enqueued step, any failure leaves work on the stream
+  for (size_t g = 0; g < Lo.keys.size(); ++g, ++step) {
+    if ((s = hook(step)) != HP_OK) return s;
     BatchArgs A = args[g];
-    A.plans = reinterpret_cast<const DevPlan*>(d + plans_off);
-    A.tasks = reinterpret_cast<const int2*>(d + task_off[g]);
-    A.ctr = reinterpret_cast<unsigned int*>(d + ctr_off[g]);
-    A.ins = reinterpret_cast<const void* const*>(d + ptr_off);
-    A.outs = reinterpret_cast<void* const*>(d + ptr_off) + n;
-    A.wss = reinterpret_cast<unsigned char* const*>(d + ptr_off) + 2 * n;
-    hp_status s = launch_batch(keys[g].first, keys[g].second, A, grid[g], kBatchGroupWaves, lds, slot.st);
-    if (s != HP_OK) return s;
+    A.plans = reinterpret_cast<const DevPlan*>(d + Lo.plans_off);
+    A.tasks = reinterpret_cast<const int2*>(d + Lo.task_off[g]);
+    A.ctr = reinterpret_cast<unsigned int*>(d + Lo.ctr_off[g]);
+    A.ins = reinterpret_cast<const void* const*>(d + Lo.ptr_off);
+    A.outs = reinterpret_cast<void* const*>(d + Lo.ptr_off) + n;
+    A.wss = reinterpret_cast<unsigned char* const*>(d + Lo.ptr_off) + 2 * n;
+    s = launch_batch(Lo.keys[g].first, Lo.keys[g].second, A, grid[g], kBatchGroupWaves, lds, slot.st);
+    if (s != HP_OK) {
+      *drain = true;
+      return s;
+    }
   }
-  if (!folds.empty()) {
-    hp_status s = launch_fold(reinterpret_cast<const DevPlan*>(d + plans_off),
-                              reinterpret_cast<const FoldTask*>(d + fold_off), (int)folds.size(),
-                              reinterpret_cast<void* const*>(d + ptr_off) + n,
-                              reinterpret_cast<unsigned char* const*>(d + ptr_off) + 2 * n, slot.st);
-    if (s != HP_OK) return s;
+  if (!Lo.folds.empty()) {
+    if ((s = hook(step)) != HP_OK) return s;
+    s = launch_fold(reinterpret_cast<const DevPlan*>(d + Lo.plans_off),
+                    reinterpret_cast<const FoldTask*>(d + Lo.fold_off), (int)Lo.folds.size(),
+                    reinterpret_cast<void* const*>(d + Lo.ptr_off) + n,
+                    reinterpret_cast<unsigned char* const*>(d + Lo.ptr_off) + 2 * n, slot.st);
+    if (s != HP_OK) {
+      *drain = true;
+      return s;
+    }
+    ++step;
   }
-  if (hipEventRecord(slot.ev, slot.st) != hipSuccess) return fail(HP_EDEVICE, "event record failed");
+  if ((s = hook(step)) != HP_OK) return s;
+  if (hipEventRecord(slot.ev, slot.st) != hipSuccess) {
+    *drain = true;
+    return fail(HP_EDEVICE, "event record failed");
+  }
   return HP_OK;
 }
 
@@ -233,6 +339,19 @@ void finish_slot(hp_server_s* S, Slot& slot, int32_t status) {
   slot.charged = 0;
   slot.reqs.clear();
   slot.busy = false;
+  slot.err = HP_OK;
+}
+
+// A launch failed after some of its steps were enqueued on the slot's stream: keep
+// the slot busy until that work has finished (its staging buffer and arena are in
+// use until then), and fail its requests only at that point.
+void drain_failed_slot(hp_server_s* S, Slot& slot, int32_t status) {
+  slot.err = status;
+  if (S->fake) return;  // fake_done was set by the executor
+  if (hipEventRecord(slot.ev, slot.st) != hipSuccess) {
+    (void)hipStreamSynchronize(slot.st);  // cannot poll: wait here
+    finish_slot(S, slot, status);
+  }
 }
 
 void scheduler(hp_server_s* S) {
@@ -244,10 +363,10 @@ void scheduler(hp_server_s* S) {
     for (Slot& sl : S->slots) {
       if (!sl.busy) continue;
       if (S->fake) {
-        if (S->now() >= sl.fake_done) finish_slot(S, sl, HP_OK);
+        if (S->now() >= sl.fake_done) finish_slot(S, sl, sl.err);
       } else {
         const hipError_t q = hipEventQuery(sl.ev);
-        if (q == hipSuccess) finish_slot(S, sl, HP_OK);
+        if (q == hipSuccess) finish_slot(S, sl, sl.err);
         else if (q != hipErrorNotReady) finish_slot(S, sl, HP_EDEVICE);
       }
       any_busy = any_busy || sl.busy;
@@ -270,12 +389,16 @@ void scheduler(hp_server_s* S) {
       if (full || waited || !any_busy || S->stop.load()) {
         std::vector<Request*> rs;
         size_t charge = 0;
+        Tally tally;
         for (auto it = S->pending.begin(); it != S->pending.end() && (int64_t)rs.size() < S->cfg.max_batch;) {
           Request& r = S->reqs[*it];
-          if (S->in_use + charge + r.bytes <= S->cfg.hbm_budget) {
+          // a request joins when its bytes fit the HBM budget and its descriptors and
+          // workspace fit what is left of the slot arena; otherwise it stays pending
+          if (S->in_use + charge + r.bytes <= S->cfg.hbm_budget && tally.total_with(r) <= free_slot->cap) {
             r.info.t_admit_us = t;
             rs.push_back(&r);
             charge += r.bytes;
+            tally.add(r);
             it = S->pending.erase(it);
           } else {
             // bounded bypass: later requests may pass a request that does not fit
@@ -289,6 +412,7 @@ void scheduler(hp_server_s* S) {
           sl.busy = true;
           sl.charged = charge;
           sl.batch_id = ++S->batches;
+          sl.err = HP_OK;
           S->in_use += charge;
           S->max_in_use = std::max(S->max_in_use, S->in_use);
           sl.reqs.clear();
@@ -297,19 +421,15 @@ void scheduler(hp_server_s* S) {
             r->info.t_launch_us = t;
             r->info.batch_id = sl.batch_id;
           }
-          hp_status s = HP_OK;
-          if (S->fail_every > 0 && sl.batch_id % S->fail_every == 0) {
-            s = HP_EDEVICE;  // test hook: this batch fails before launch
-          } else if (S->fake) {
-            double work = 0;
-            for (Request* r : rs) work += (double)r->L.info.in_bytes;
-            sl.fake_done = t + 5.0 + work / 4.0e3;  // 4 GB/s-ish pretend device
-          } else {
-            lk.unlock();
-            s = launch_slot(S, sl, rs);
-            lk.lock();
+          bool drain = false;
+          lk.unlock();
+          hp_status s = launch_slot(S, sl, rs, &drain);
+          lk.lock();
+          if (s != HP_OK) {
+            const int32_t st = s == HP_ETOOBIG ? HP_ETOOBIG : HP_EDEVICE;
+            if (drain) drain_failed_slot(S, sl, st);
+            else finish_slot(S, sl, st);
           }
-          if (s != HP_OK) finish_slot(S, sl, s == HP_ETOOBIG ? HP_ETOOBIG : HP_EDEVICE);
           launched = true;
         }
       }
@@ -328,7 +448,8 @@ extern "C" hp_status hp_server_create(const hp_server_cfg* cfg, hp_server_t* out
   if (!cfg || !out) return fail(HP_EINVAL, "null argument");
   *out = nullptr;
   if (cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 1 || cfg->max_batch > 65536 ||
-      cfg->window_us < 0 || cfg->queue_cap < 1 || cfg->hbm_budget == 0 || cfg->slot_bytes < 4096)
+      cfg->window_us < 0 || cfg->queue_cap < 1 || cfg->hbm_budget == 0 || cfg->slot_bytes < 4096 ||
+      cfg->fail_every_nth_batch < 0 || cfg->fail_step < 0)
     return fail(HP_EINVAL, "bad server configuration");
   hp_server_s* S = new (std::nothrow) hp_server_s;
   if (!S) return fail(HP_ENOMEM, "host allocation failed");
@@ -337,6 +458,7 @@ extern "C" hp_status hp_server_create(const hp_server_cfg* cfg, hp_server_t* out
   S->fail_every = cfg->fail_every_nth_batch;
   S->t0 = Clock::now();
   S->slots.resize((size_t)cfg->streams);
+  for (Slot& sl : S->slots) sl.cap = cfg->slot_bytes;
   if (!S->fake) {
     if (hipGetDevice(&S->device) != hipSuccess) {
       delete S;
@@ -345,7 +467,6 @@ extern "C" hp_status hp_server_create(const hp_server_cfg* cfg, hp_server_t* out
     if (hipDeviceGetAttribute(&S->cus, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess)
       S->cus = 256;
     for (Slot& sl : S->slots) {
-      sl.cap = cfg->slot_bytes;
       if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
           hipMalloc(&sl.d_arena, sl.cap) != hipSuccess || hipHostMalloc(&sl.h_stage, sl.cap) != hipSuccess) {
@@ -409,6 +530,16 @@ extern "C" hp_status hp_submit(hp_server_t S, const hp_nest* nest, const void* d
   r.bytes = r.L.info.in_bytes + r.L.info.out_bytes + r.L.info.workspace_bytes;
   if (r.bytes > S->cfg.hbm_budget)
     return fail(HP_ETOOBIG, "request needs %zu bytes, budget is %zu", r.bytes, (size_t)S->cfg.hbm_budget);
+  r.key = std::make_pair(family_of(r.L.dp), (int)r.L.dp.chunk);
+  r.ntask = r.L.dp.grid;
+  r.nfold = fold_task_count(r.L.dp);
+  r.ws = align_up(r.L.info.workspace_bytes, 256);
+  {
+    const size_t arena = Tally().total_with(r);
+    if (arena > S->cfg.slot_bytes)
+      return fail(HP_ETOOBIG, "request needs %zu bytes of slot arena, slot_bytes is %zu", arena,
+                  (size_t)S->cfg.slot_bytes);
+  }
   r.nest = *nest;
   r.in = d_in;
   r.out = d_out;

@@ -1,5 +1,5 @@
 // Stencils tiled through local memory (the paper's second class of multi-level
-// algorithms, section 4, and its ghost surfaces, section 6): `steps` five-point
+// algorithms, section 2, and its ghost surfaces, section 4): `steps` five-point
 // Jacobi sweeps of a 2-D float array with fixed boundary cells,
 //   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1])).
 // Each workgroup owns a TH x TW output tile.  It reads the tile plus a ghost

@@ -198,12 +198,16 @@ def test_xcd_scope_planning():
     assert i["units"][0][0] == 8 and i["grid"] == 8 * 16 and i["gsplit"] == 16
     i = hp.inspect((64, 64, 256), (hp.SUM, hp.SUM, hp.SUM), hp.F32, ["X", ("GW", {"G": 4, "W": 4}), "V"])
     assert i["map"] == ["X", "GW", "V"] and i["grid"] == 32 and i["gsplit"] == 32
+    # a grid of exactly 8 (X alone, here collapsed with W): workgroup b is unit b
+    i = hp.inspect((40, 64, 256), (hp.NONE, hp.SUM, hp.SUM), hp.F32, [("XW", {"W": 2}), ("W", {"W": 4}), "V"])
+    assert i["map"][0] == "XW" and i["grid"] == 8 and i["units"][0] == (8, 2, 1)
+    i = hp.inspect((4, 64), (hp.NONE, hp.SUM), hp.I32, ["X", "V"])
+    assert i["grid"] == 8
     bad = [(c3, ["G", "X", "V", "L"], 0, "HP_EINVAL", "already uses the grid"),
            (c3, ["X", "GW", "V", "V"], hp.FLAG_NO_XCD, "HP_EINVAL", "NO_XCD"),
            (c3, ["X", "X", "V", "V"], 0, "HP_EINVAL", "both use"),
            (c3, [("X", {"G": 4}), "GW", "V", "V"], 0, "HP_EINVAL", "8 units"),
-           (c3, ["XG", "W", "V", "V"], 0, "HP_EINVAL", "both X and G"),
-           (((4, 64), (hp.NONE, hp.SUM), hp.I32), ["X", "V"], 0, "HP_EUNSUPPORTED", "at least 16")]
+           (c3, ["XG", "W", "V", "V"], 0, "HP_EINVAL", "both X and G")]
     for (ext, ops, dt), m, fl, status, words in bad:
         with pytest.raises(hp.HPError) as e:
             hp.inspect(ext, ops, dt, m, fl)
