@@ -38,6 +38,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def progress(msg: str):
+    """A progress line on stderr as each part of the benchmark ends."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def pct(xs, q):
     xs = sorted(xs)
     k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
@@ -155,35 +160,63 @@ def ingest_counters(fetch_csv, write_csv, kernel, nbytes, copy_bytes=1 << 30, sq
     print(json.dumps(d))
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), as lscpu prints it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_host, ext, ops, got_rows):
-    """Oracle on the host cores: the full workload with every core (median of 3),
-    plus the error statement of the GPU result against it."""
+    """Oracle on the host cores: the full workload with every core (median of the
+    runs made in about 10 s), the same on one core, and the error statement of the
+    GPU result against it."""
     import numpy as np
 
     import oracle
     threads = max(1, min(64, os.cpu_count() or 1))
     n_out = ext[0]
-    times = []
-    ref = None
-    # repeat the full workload until about 10 s of CPU time is spent (at least 3 runs)
-    t_start = time.perf_counter()
-    while len(times) < 3 or (time.perf_counter() - t_start < 10.0 and len(times) < 1000):
-        t0 = time.perf_counter()
-        ref = oracle.reduce(x_host, ext, ops, oracle.F32, threads=threads)
-        times.append(time.perf_counter() - t0)
-    t = statistics.median(times)
     nbytes = x_host.nbytes + n_out * 8
+
+    def timed(th, budget_s, min_runs):
+        times, ref = [], None
+        t_start = time.perf_counter()
+        while len(times) < min_runs or (time.perf_counter() - t_start < budget_s and len(times) < 1000):
+            t0 = time.perf_counter()
+            ref = oracle.reduce(x_host, ext, ops, oracle.F32, threads=th)
+            times.append(time.perf_counter() - t0)
+        return statistics.median(times), len(times), ref
+
+    t, runs, ref = timed(threads, 10.0, 3)
+    t1, runs1, ref1 = timed(1, 8.0, 2)
     s = oracle.abs_sum(x_host, ext, ops, oracle.F32, threads=threads)
     ok, plain, scaled = oracle.within_tolerance(got_rows, ref, s, 1e-6)
     return {
         "value": round(nbytes / t / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-        "sample": f"full workload ({n_out} outputs, {x_host.nbytes >> 20} MiB) repeated for ~10 s, median of {len(times)} runs, "
+        "sample": f"full workload ({n_out} outputs, {x_host.nbytes >> 20} MiB) repeated for ~10 s, median of {runs} runs, "
                   f"fp64 Neumaier sequential C, outputs split over {threads} threads",
-        "seconds": round(t, 4),
+        "seconds": round(t, 4), "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+        "single_core": {"value": round(nbytes / t1 / 1e9, 3), "unit": "GB/s", "cores": 1, "seconds": round(t1, 4),
+                        "sample": f"the same full workload on one thread, median of {runs1} runs",
+                        "bit_identical_to_all_cores": bool(np.array_equal(ref, ref1))},
     }, {"all_outputs_checked": int(n_out), "within_1e-6": ok, "max_rel_err": plain,
         "max_scaled_err": scaled,
         "worst_condition_number": float(np.max(s / np.maximum(np.abs(ref), 1e-300))),
         "rule": "|gpu - fp64 oracle| <= 1e-6 * max(|oracle|, 2^-24 * sum|a|) per output"}
+
+
+def error_statement(v) -> dict:
+    """The summary of oracle.verify that the bench line carries."""
+    keys = ("ok", "nests", "int_nests", "int_nests_mismatched", "float_nests", "float_outputs", "max_rel_err",
+            "max_scaled_err", "worst_condition_number")
+    d = {k: v[k] for k in keys}
+    d["rule"] = "ints bit-exact; floats |gpu - fp64 oracle| <= 1e-6 * max(|oracle|, 2^-24 * sum|a|) per output"
+    return d
 
 
 def extra_int_workloads(steps, warmup, stream):
@@ -284,7 +317,7 @@ def stencils(stream, steps=20, warmup=3):
     return res
 
 
-def batched_vs_plain(stream, steps=20, warmup=3, plain=True):
+def batched_vs_plain(stream, steps=20, warmup=3, plain=True, verify=True):
     """10,000 uneven bf16 nests: one persistent launch replayed from a hipGraph vs one
     launch per nest (eager, and all launches captured in one graph).  Same plans, so
     the outputs are compared bit for bit."""
@@ -327,6 +360,12 @@ def batched_vs_plain(stream, steps=20, warmup=3, plain=True):
     wall_b, ev_b = timed(lambda: b.run(stream), steps, warmup)
     got_b = out_a.cpu().numpy()
     nbytes = st["bytes"]
+    err = None
+    if verify:
+        import oracle
+        cases = [(host[bw.offsets[i]:bw.offsets[i] + n.elems].reshape(n.extents), n.extents, n.ops, oracle.BF16,
+                  got_b[oo[i]:oo[i + 1]]) for i, n in enumerate(bw.nests)]
+        err = error_statement(oracle.verify(cases))
     if not plain:
         b.close()
         return {"nests": len(nests), "bytes": nbytes, "persistent_launches": st["launches"], "tasks": st["tasks"],
@@ -349,60 +388,106 @@ def batched_vs_plain(stream, steps=20, warmup=3, plain=True):
         "plain_launches_in_one_graph": {"p50_us": round(pct(ev_g, 50) * 1e3, 1),
                                         "GBps": round(nbytes / (pct(ev_g, 50) * 1e-3) / 1e9, 1)},
         "bit_identical_to_plain": bool(np.array_equal(got_b, got_p)),
+        "error_vs_fp64_oracle": err,
     }
     res["speedup_vs_plain"] = round(res["plain_one_launch_per_nest"]["p50_us"] / res["batched_graph"]["p50_us"], 2)
     del dev, out_a, out_b
     return res
 
 
-def serving(duration_s=3.0, rate=20000.0, warmup_s=1.0):
-    """Open-loop Poisson stream of mixed 2-4 level requests admitted by a 64 GiB
-    budget; latency from scheduled arrival to observed completion, over the requests
-    that arrive after the first warmup_s seconds."""
+class ServingPools:
+    """The request stream's two 1 GiB payload pools (int32 and fp32), on the host and
+    on the device, shared by the serving runs."""
+
+    def __init__(self):
+        import torch
+
+        import workloads
+        st = workloads.c5_stream(duration_s=0.0, pool_elems=1 << 28)
+        self.seed = st.seed
+        self.pi, self.pf = st.pool_i32(), st.pool_f32()
+        self.di, self.df = torch.from_numpy(self.pi).cuda(), torch.from_numpy(self.pf).cuda()
+
+
+def serve_stream(pools, duration_s, rate, warmup_s, verify):
+    """Replay one open-loop Poisson stream through a server; latency is measured
+    from each request's scheduled arrival to its observed completion."""
     import numpy as np
     import torch
 
     import paper_2309_01906_amd as hp
     import workloads
-    st = workloads.c5_stream(duration_s=duration_s, rate=rate, pool_elems=1 << 28)
-    di = torch.from_numpy(st.pool_i32()).cuda()
-    df = torch.from_numpy(st.pool_f32()).cuda()
+    st = workloads.c5_stream(duration_s=duration_s + warmup_s, rate=rate, pool_elems=1 << 28)
+    assert st.seed == pools.seed
     reqs = st.requests
-    out_sizes, kinds = [], []
-    for r in reqs:
-        inf = hp.inspect(r.nest.extents, r.nest.ops, r.nest.dtype)
-        out_sizes.append(inf["n_out"])
-        kinds.append(inf["out_dtype"])
-    tot = int(sum(out_sizes)) + len(reqs)
-    out = torch.zeros(tot, dtype=torch.float64, device="cuda")  # 8 bytes per output slot
+    out_sizes = [hp.inspect(r.nest.extents, r.nest.ops, r.nest.dtype)["n_out"] for r in reqs]
+    out = torch.zeros(int(sum(out_sizes)) + len(reqs), dtype=torch.float64, device="cuda")  # 8 B per output
     offs = np.concatenate([[0], np.cumsum(out_sizes)])
-    ins = [(di if r.pool == 0 else df).data_ptr() + 4 * r.offset for r in reqs]
+    ins = [(pools.di if r.pool == 0 else pools.df).data_ptr() + 4 * r.offset for r in reqs]
     outs = [out.data_ptr() + 8 * int(o) for o in offs[:-1]]
     nests = [(r.nest.extents, r.nest.ops, r.nest.dtype) for r in reqs]
     with hp.Server(hbm_budget=64 << 30, slot_bytes=256 << 20, streams=4, max_batch=512, window_us=30) as srv:
         t0 = srv.now_us() + 5000.0
-        arrivals = [t0 + r.t_arrival_us for r in reqs]
-        tk = srv.replay(nests, ins, outs, arrivals)
+        tk = srv.replay(nests, ins, outs, [t0 + r.t_arrival_us for r in reqs])
         infos = [srv.wait(t) for t in tk]
         stats = srv.stats()
-    ok = all(i["status"] == 0 for i in infos)
+    arr = np.array([i["t_arrival_us"] - t0 for i in infos])
     lat = np.array([i["t_done_us"] - i["t_arrival_us"] for i in infos])
-    steady = np.array([r.t_arrival_us >= warmup_s * 1e6 for r in reqs])
+    steady = arr >= warmup_s * 1e6
     ls = lat[steady]
     nb = sum(int(np.prod(r.nest.extents)) * 4 for r, k in zip(reqs, steady) if k)
     t_first = min(i["t_arrival_us"] for i, k in zip(infos, steady) if k)
     t_last = max(i["t_done_us"] for i, k in zip(infos, steady) if k)
-    del di, df, out
-    return {
-        "requests": len(reqs), "offered_rate_per_s": rate, "duration_s": duration_s, "warmup_s": warmup_s,
-        "all_ok": ok, "batches": stats["batches"],
+    res = {
+        "requests": len(reqs), "measured_requests": int(steady.sum()), "offered_rate_per_s": rate,
+        "duration_s": duration_s, "warmup_s": warmup_s,
+        "all_ok": all(i["status"] == 0 for i in infos), "failed": stats["failed"], "batches": stats["batches"],
         "p50_us": round(float(np.percentile(ls, 50)), 1), "p99_us": round(float(np.percentile(ls, 99)), 1),
         "p999_us": round(float(np.percentile(ls, 99.9)), 1), "max_us": round(float(ls.max()), 1),
         "GBps": round(nb / (t_last - t_first) / 1e3, 2),
-        "including_warmup": {"p50_us": round(stats["p50_us"], 1), "p99_us": round(stats["p99_us"], 1),
-                             "GBps": round(stats["gbps"], 2)},
-        "bytes": stats["bytes"], "max_in_flight_bytes": stats["max_in_use_bytes"],
     }
+    if verify:
+        import oracle
+        got = out.cpu().numpy()
+        cases = []
+        for k, r in enumerate(reqs):
+            pool = pools.pi if r.pool == 0 else pools.pf
+            x = pool[r.offset:r.offset + r.nest.elems].reshape(r.nest.extents)
+            g = got[offs[k]:offs[k + 1]]  # one 8-byte slot per output; int32 outputs fill the first half
+            kind = hp.inspect(r.nest.extents, r.nest.ops, r.nest.dtype)["out_dtype"]
+            g = g.view(np.int64) if kind == hp.I64 else g.view(np.int32)[:g.size].copy() if kind == hp.I32 else g
+            cases.append((x, r.nest.extents, r.nest.ops, r.nest.dtype, g))
+        res["error_vs_fp64_oracle"] = error_statement(oracle.verify(cases))
+        # start-up: p99 per 100 ms of arrival time over the first two seconds
+        res["startup_p99_us_per_100ms"] = [round(float(np.percentile(lat[(arr >= a) & (arr < a + 1e5)], 99)), 1)
+                                           for a in np.arange(0, 2e6, 1e5) if np.any((arr >= a) & (arr < a + 1e5))]
+        res["including_warmup"] = {"p50_us": round(stats["p50_us"], 1), "p99_us": round(stats["p99_us"], 1),
+                                   "GBps": round(stats["gbps"], 2)}
+        res["bytes"] = stats["bytes"]
+        res["max_in_flight_bytes"] = stats["max_in_use_bytes"]
+    del out
+    return res
+
+
+def serving(duration_s=10.0, rate=20000.0, warmup_s=1.0, sweep=True):
+    """Open-loop Poisson stream of mixed 2-4 level requests admitted by a 64 GiB
+    budget: 10 s measured after a 1 s warm-up at the offered 20k req/s, every result
+    checked against the oracle; then a rate sweep (shorter runs) until p99 passes
+    1 ms, to find the server's capacity."""
+    pools = ServingPools()
+    res = serve_stream(pools, duration_s, rate, warmup_s, verify=True)
+    if sweep:
+        res["rate_sweep"] = []
+        r = 2 * rate
+        while r <= 2.56e6:
+            s = serve_stream(pools, 1.5, r, 0.5, verify=False)
+            res["rate_sweep"].append({k: s[k] for k in ("offered_rate_per_s", "measured_requests", "all_ok", "p50_us",
+                                                        "p99_us", "GBps", "batches")})
+            if s["p99_us"] > 1000.0 or not s["all_ok"]:
+                break
+            r *= 2
+    del pools
+    return res
 
 
 def main():
@@ -414,6 +499,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-s", type=float, default=10.0, help="measured seconds of the serving run")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the serving rate sweep")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
     ap.add_argument("--batched-only", action="store_true",
@@ -449,7 +536,8 @@ def main():
         tc = os.path.join(ROOT, "paper_2309_01906_amd", "tune_gfx950.txt")
         if os.path.exists(tc):
             hp.tune_cache_load(tc)
-        print(json.dumps({"batched": batched_vs_plain(stream, args.steps, args.warmup, plain=False)}), flush=True)
+        print(json.dumps({"batched": batched_vs_plain(stream, args.steps, args.warmup, plain=False, verify=False)}),
+              flush=True)
         return
     nest = workloads.C2
     x_host = workloads.c2_input()
@@ -506,21 +594,27 @@ def main():
                      "kernel": plan.info["kernel_name"], "algorithmic_bytes_per_launch": nbytes,
                      "kernel_hash": kernel_hash(), "utilisation": utilisation_from_profiles(avg_ev)},
     }
+    progress(f"headline nest {round(achieved, 1)} GB/s by kernel events")
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(x_host, nest.extents, nest.ops, got)
         line["cpu_baseline"] = cb
         line["error_vs_fp64_oracle"] = err
+        progress("oracle timed and outputs checked")
     if not args.no_extras:
         line["extras"] = extra_int_workloads(min(args.steps, 200), min(args.warmup, 20), stream)
+        progress("2- and 4-level integer nests done")
         tc = os.path.join(ROOT, "paper_2309_01906_amd", "tune_gfx950.txt")
         if os.path.exists(tc):
             hp.tune_cache_load(tc)
         if not args.no_batch:
             line["batched_vs_plain"] = batched_vs_plain(stream)
+            progress("batched nests done")
         if not args.no_serving:
-            line["serving"] = serving()
+            line["serving"] = serving(duration_s=args.serving_s, sweep=not args.no_sweep)
+            progress("serving done")
         line["ordered_products"] = ordered_products(stream)
         line["stencils"] = stencils(stream)
+        progress("ordered products and stencils done")
     plan.close()
     print(json.dumps(line), flush=True)
 

@@ -145,6 +145,12 @@ typedef struct hp_plan_info {
   int64_t strips[HP_MAX_DEPTH];    /* serial strips per level per unit */
   int32_t nseg;                    /* reducing segments (runs of levels combined as one) */
   int32_t kernel;                  /* hp_kernel: the kernel variant hp_run launches */
+  int64_t flat_block;              /* 0, or the block length when the plan's reducing levels are the aligned
+                                      interior of each output's contiguous block (a single SUM / MIN / MAX
+                                      reduction whose block is not a multiple of the 16-byte vector: the
+                                      planner maps the interior with 16-byte loads and spreads the elements
+                                      before and after it over the output's threads); depth, scopes, units
+                                      and strips then describe the interior view */
 } hp_plan_info;
 
 /* Kernel variants (hp_plan_info.kernel).  Every variant runs the same level

@@ -184,3 +184,54 @@ def within_tolerance(got: np.ndarray, ref: np.ndarray, abs_sum_ref: np.ndarray, 
         scaled = np.where(scale > 0, err / scale, np.where(err == 0, 0.0, np.inf))
     ok = bool(np.all(scaled <= rel))
     return ok, float(plain.max(initial=0.0)), float(scaled.max(initial=0.0))
+
+
+def verify(cases, rel: float = 1e-6, workers: int | None = None) -> dict:
+    """Check many device results against the oracle (a thread pool: the C calls
+    release the GIL).  ``cases`` yields (x, extents, ops, dtype, got) per nest.
+    Integer nests must match bit for bit; float nests must satisfy
+    ``within_tolerance`` output by output.  Returns counts, the largest plain and
+    scaled errors, the worst condition number sum|a| / |sum a| over the float
+    outputs, and the first failing cases."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    cases = list(cases)
+    if workers is None:
+        workers = max(1, min(16, os.cpu_count() or 1))
+
+    def one(k):
+        x, ext, ops, dt, got = cases[k]
+        ref = reduce(x, ext, ops, dt)
+        got = np.asarray(got)
+        if dt == I32:
+            bad = int(np.count_nonzero(got.reshape(ref.shape) != ref)) if got.size == ref.size else ref.size
+            return k, True, bad, None
+        s = abs_sum(x, ext, ops, dt) if any(o != NONE for o in ops) else np.abs(ref.astype(np.float64))
+        return k, False, None, (np.asarray(got, np.float64).reshape(-1), ref.astype(np.float64), s)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(one, range(len(cases))))
+    n_int = sum(1 for r in res if r[1])
+    int_bad = [(r[0], r[2]) for r in res if r[1] and r[2]]
+    fl = [r for r in res if not r[1]]
+    out = {"nests": len(cases), "int_nests": n_int, "int_nests_mismatched": len(int_bad),
+           "float_nests": len(fl), "float_outputs": 0, "float_within": True, "max_rel_err": 0.0,
+           "max_scaled_err": 0.0, "worst_condition_number": 0.0, "failures": [k for k, _ in int_bad[:5]]}
+    if fl:
+        got = np.concatenate([r[3][0] for r in fl])
+        ref = np.concatenate([r[3][1] for r in fl])
+        s = np.concatenate([r[3][2] for r in fl])
+        ok, plain, scaled = within_tolerance(got, ref, s, rel)
+        with np.errstate(divide="ignore"):
+            cond = float(np.max(np.where(ref != 0, s / np.abs(ref), np.where(s == 0, 1.0, np.inf))))
+        out.update(float_outputs=int(got.size), float_within=ok, max_rel_err=plain, max_scaled_err=scaled,
+                   worst_condition_number=cond)
+        if not ok:
+            for r in fl:
+                g, f, a = r[3]
+                if not within_tolerance(g, f, a, rel)[0]:
+                    out["failures"].append(r[0])
+                    if len(out["failures"]) >= 10:
+                        break
+    out["ok"] = not int_bad and out["float_within"]
+    return out

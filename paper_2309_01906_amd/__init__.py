@@ -54,7 +54,7 @@ class PlanInfo(ctypes.Structure):
                 ("gsplit", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t), ("lds_bytes", ctypes.c_size_t),
                 ("scopes", ctypes.c_uint32 * MAX_DEPTH), ("units", (ctypes.c_uint32 * 3) * MAX_DEPTH),
                 ("strips", ctypes.c_int64 * MAX_DEPTH), ("nseg", ctypes.c_int32),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("flat_block", ctypes.c_int64)]
 
 
 _lib = None
@@ -159,6 +159,7 @@ def _info_dict(inf: PlanInfo) -> dict:
                 for i in range(d)],
         "units": [tuple(inf.units[i][a] for a in range(3)) for i in range(d)],
         "strips": [inf.strips[i] for i in range(d)],
+        "flat_block": inf.flat_block,
     }
 
 

@@ -79,6 +79,15 @@ struct alignas(16) DevPlan {
   int32_t pad3;
   int64_t ord_block;                // ordered products: elements per output
   int64_t ord_span;                 // ordered products: elements per chunk (gsplit chunks per output)
+  // Contiguous blocks at any element offset (a single reduction whose block length
+  // is not a multiple of the 16-byte vector): output o's block is the flat_b
+  // elements at s = o * flat_b.  The reducing levels of the plan cover its aligned
+  // interior, flat_e elements from s + h, h = (-s) mod chunk; the other elements
+  // (h before it, flat_b - h - flat_e after it) are spread over the flat_units
+  // threads that share the output and added before the combine.  0: off.
+  int64_t flat_b;
+  int64_t flat_e;
+  int64_t flat_units;
   // innermost segment, walked as one batched stream: its levels with more than one
   // strip, outer to inner ("inner dims")
   int32_t a;                        // first level of the innermost segment
@@ -104,7 +113,21 @@ struct Lowered {
 // Fill `out` from nest + map; sets the thread-local error text on failure.
 // force_nw > 0 (batched plans): the plan must use exactly that many waves per
 // workgroup; the automatic map gives them to its wave level.
-hp_status lower(const hp_nest* nest, const hp_level_map* map, uint32_t flags, Lowered* out, int force_nw = 0);
+// flat_block > 0: the nest's reducing levels are the aligned interior of blocks of
+// flat_block contiguous elements (see DevPlan::flat_b); the planner and the tuner
+// make such views of single-reduction nests whose blocks are not vector multiples.
+hp_status lower(const hp_nest* nest, const hp_level_map* map, uint32_t flags, Lowered* out, int force_nw = 0,
+                int64_t flat_block = 0);
+
+// Whether a nest may be viewed as flat blocks: one reduction (SUM, MIN or MAX over
+// every reducing level) of int32 / float elements whose block is long enough to
+// hold an aligned interior; *block receives the block length and *p the number of
+// output levels.  vec = elements per 16-byte vector.
+bool flat_candidate(const hp_nest* nest, int* p, int64_t* block, int* vec);
+// The aligned interior of such a block of b elements: the largest multiple of
+// `unit` (a multiple of vec) that fits after the up to vec - 1 elements before the
+// block's first aligned vector.
+int64_t flat_interior(int64_t b, int vec, int64_t unit);
 
 // Thread-local error text.
 hp_status fail(hp_status s, const char* fmt, ...);

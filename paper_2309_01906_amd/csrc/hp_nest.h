@@ -555,11 +555,52 @@ __device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const D
   return a;
 }
 
+// Flat blocks (DevPlan::flat_b): add the elements of the output's block that lie
+// outside its aligned interior -- the h = (-s) mod chunk before it and the rest
+// after it -- spread over the flat_units threads that share the output (thread of
+// rank r takes elements r, r + flat_units, ...; consecutive ranks read consecutive
+// elements).  Every element of the block is inside the array, so no load leaves it.
+template <class T>
+struct RestAdd;
+template <>
+struct RestAdd<FloatT<float>> {
+  __device__ static __forceinline__ void run(FAcc& a, float x, int) { FloatT<float>::add(a, x, 0, 0); }
+};
+template <>
+struct RestAdd<FloatT<uint16_t>> {
+  __device__ static __forceinline__ void run(FAcc& a, uint16_t x, int) {
+    FloatT<uint16_t>::add(a, bf16_lo((uint32_t)x), 0, 0);
+  }
+};
+template <>
+struct RestAdd<IntT> {
+  __device__ static __forceinline__ void run(IAcc& a, int x, int op) { IntT::add(a, x, 0, op); }
+};
+
+template <class T, int KD>
+__device__ __forceinline__ typename T::Acc flat_rest(const DevPlan& P, const typename T::Raw* __restrict__ in, long long s,
+                                                  typename T::Acc a, const Thread<KD>& th) {
+  const long long h = (-s) & (long long)(P.chunk - 1);
+  const long long n = P.flat_b - P.flat_e;  // h before the interior, n - h after it
+  const long long tail0 = s + P.flat_e;     // element j >= h of the rest sits at tail0 + j
+  long long r = 0;
+#pragma unroll
+  for (int m = 0; m < KD; ++m)
+    if (m >= P.p && m < P.depth) {
+      const DevLevel& L = P.lv[m];
+      r = r * ((long long)L.gf * L.wf * L.vf) + th.targ[m] / L.chunk;
+    }
+  const int op = P.seg[0].op;
+  for (long long j = r; j < n; j += P.flat_units) RestAdd<T>::run(a, in[j < h ? s + j : tail0 + j], op);
+  return a;
+}
+
 // Reduce the current output's block; returns segment P.gq's value (the output, or
 // this workgroup's partial of it when that segment spans workgroups).
 template <class T, int C, int NS, int U, int KD, bool LEAN, bool PF = true>
 __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const typename T::Raw* __restrict__ in,
-                                                        long long base, bool vnone, const Thread<KD>& th, char* lds) {
+                                                        long long base, bool vnone, const Thread<KD>& th, char* lds,
+                                                        long long flat_s = 0) {
   using Acc = typename T::Acc;
   constexpr int NO = NS > 1 ? NS - 1 : 1;
   const int inner = P.nseg - 1;
@@ -605,6 +646,9 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
   // combine the innermost segment's lane partials, feed its value to the parent
   // segment, then finish the outer segments whose strips all end here
   auto consume = [&](Acc ai) {
+    // flat blocks have one segment walked in one outer iteration: the rest of the
+    // block joins the lane partials before they are combined
+    if (P.flat_b && vnone) ai = flat_rest<T, KD>(P, in, flat_s, ai, th);
     ai = combine_seg<T, KD>(P, P.seg[inner], ai, th, lds);
     if (inner == stop) {
       fin = ai;
@@ -847,7 +891,10 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
         }
       }
     } else {
-      const typename T::Acc a = reduce_block<T, C, NS, U, KD, LEAN, PF>(P, in, off + base_red, vnone, th, lds);
+      // flat blocks: the aligned interior starts h elements into the block
+      const long long h = P.flat_b ? ((-off) & (long long)(P.chunk - 1)) : 0;
+      const typename T::Acc a =
+          reduce_block<T, C, NS, U, KD, LEAN, PF>(P, in, off + h + base_red, vnone, th, lds, off);
       if (P.gmode == GCOMB_NONE) {
         if (vnone && red_writer) {
           if constexpr (T::kFloat) store_flt(P, out, o, (double)a.s + (double)a.c);

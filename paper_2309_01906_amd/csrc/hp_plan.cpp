@@ -265,7 +265,42 @@ static hp_status lower_ordered(const hp_nest* n, const hp_level_map* map_in, uin
   return HP_OK;
 }
 
-hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw) {
+bool flat_candidate(const hp_nest* n, int* p_out, int64_t* block, int* vec) {
+  if (n->dtype != HP_I32 && n->dtype != HP_F32 && n->dtype != HP_BF16) return false;
+  const int d = n->depth;
+  int p = d;
+  for (int l = 0; l < d; ++l)
+    if (n->op[l] != HP_OP_NONE) {
+      p = l;
+      break;
+    }
+  if (p == d) return false;
+  const int op = n->op[p];
+  if (op != HP_OP_SUM && op != HP_OP_MIN && op != HP_OP_MAX) return false;
+  int64_t b = 1;
+  for (int l = p; l < d; ++l) {
+    if (n->op[l] != op || n->extent[l] < 1) return false;
+    b *= n->extent[l];
+  }
+  const int c = 16 / elem_bytes(n->dtype);
+  if (b < 2 * c - 1) return false;  // too short for an aligned vector inside every block
+  *p_out = p;
+  *block = b;
+  *vec = c;
+  return true;
+}
+
+// The aligned interior of a flat block of b elements whose start may sit anywhere
+// inside a vector of c elements (any start when b % c != 0, else vector-aligned):
+// the largest multiple of `unit` (itself a multiple of c) that fits after the up to
+// c - 1 elements that precede the first aligned vector.
+int64_t flat_interior(int64_t b, int c, int64_t unit) {
+  const int64_t hmax = (b % c) ? c - 1 : 0;
+  return (b - hmax) / unit * unit;
+}
+
+hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw,
+                int64_t flat_block) {
   if (!n || !out) return fail(HP_EINVAL, "null argument");
   const int d = n->depth;
   if (d < 1 || d > kMaxDepth) return fail(HP_EINVAL, "depth %d outside [1, %d]", d, kMaxDepth);
@@ -298,6 +333,52 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     // the kernels are built for a full 16-byte chunk or single elements
     const int c = 16 / elem_bytes(n->dtype);
     chunk_last = (n->extent[d - 1] % c == 0) ? c : 1;
+  }
+  // A single reduction whose rows are not vector multiples, planned automatically:
+  // view each output's block as one contiguous run and map its aligned interior,
+  // so that the stream keeps 16-byte loads (section 3.5's schedule(none) masking
+  // shrinks to the few elements before and after the interior).
+  if (!map_in && !flat_block && chunk_last == 1 && !(flags & HP_FLAG_SCALAR)) {
+    int fp, c;
+    int64_t b;
+    if (flat_candidate(n, &fp, &b, &c) && flat_interior(b, c, c) >= c) {
+      hp_nest v;
+      memset(&v, 0, sizeof v);
+      v.dtype = n->dtype;
+      v.depth = fp + 1;
+      for (int l = 0; l < fp; ++l) {
+        v.extent[l] = n->extent[l];
+        v.op[l] = HP_OP_NONE;
+      }
+      v.extent[fp] = flat_interior(b, c, c);
+      v.op[fp] = n->op[fp];
+      hp_status s = lower(&v, nullptr, flags, out, force_nw, b);
+      if (s != HP_OK) return s;
+      // An interior that ends inside a strip would send every strip down the masked
+      // path; shrink it to whole strips and leave the rest (under one strip) to the
+      // threads' scalar pass.
+      const DevLevel& L = out->dp.lv[fp];
+      if (L.ragged && v.extent[fp] >= L.span && L.span % c == 0) {
+        Lowered whole;
+        v.extent[fp] = v.extent[fp] / L.span * L.span;
+        if (lower(&v, nullptr, flags, &whole, force_nw, b) == HP_OK) *out = whole;
+      }
+      return HP_OK;
+    }
+  }
+  int64_t flat_e = 0;
+  if (flat_block) {
+    // the nest is the interior view of blocks of flat_block elements
+    const int c = 16 / elem_bytes(n->dtype);
+    flat_e = 1;
+    for (int l = p; l < d; ++l) flat_e *= n->extent[l];
+    const int op = p < d ? n->op[p] : HP_OP_NONE;
+    bool one = p < d && (op == HP_OP_SUM || op == HP_OP_MIN || op == HP_OP_MAX);
+    for (int l = p; l < d && one; ++l) one = n->op[l] == op;
+    if (!one || chunk_last != c || flat_e < c || flat_e > flat_interior(flat_block, c, c))
+      return fail(HP_EINVAL, "flat view: %lld interior elements do not fit blocks of %lld", (long long)flat_e,
+                  (long long)flat_block);
+    total = total / flat_e * flat_block;
   }
 
   hp_level_map m;
@@ -361,8 +442,11 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     L.seg = -1;
   }
   dp.lv[d - 1].stride = 1;
-  for (int l = d - 2; l >= 0; --l) dp.lv[l].stride = dp.lv[l + 1].stride * dp.lv[l + 1].e;
+  for (int l = d - 2; l >= 0; --l)
+    dp.lv[l].stride = (flat_block && l == p - 1) ? flat_block : dp.lv[l + 1].stride * dp.lv[l + 1].e;
   dp.chunk = chunk_last;
+  dp.flat_b = flat_block;
+  dp.flat_e = flat_e;
 
   // ---- V axis: 64 lanes split between the levels that use it (outer = high bits)
   {
@@ -617,7 +701,16 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
   {
     int64_t vspan = 0;
     for (int l = 0; l < d; ++l) vspan += (int64_t)(dp.lv[l].vf - 1) * dp.lv[l].chunk * dp.lv[l].stride;
+    if (flat_block) vspan += dp.chunk;  // each lane's interior starts up to a vector later
     dp.vlane32 = vspan * elem_bytes(n->dtype) < ((int64_t)1 << 31) ? 1 : 0;
+  }
+  // ---- flat blocks: the threads that share one output (they spread the elements
+  // outside the interior between them)
+  if (flat_block) {
+    if (dp.nseg != 1 || dp.outer_iters != 1) return fail(HP_EINVAL, "flat view needs one reducing segment");
+    int64_t u = 1;
+    for (int l = p; l < d; ++l) u *= (int64_t)dp.lv[l].gf * dp.lv[l].wf * dp.lv[l].vf;
+    dp.flat_units = u;
   }
   // ---- kernel variant
   if (is_float) {
@@ -659,6 +752,7 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
   }
   I.nseg = dp.nseg;
   I.kernel = dp.kernel;
+  I.flat_block = flat_block;
   out->dp = dp;
   return HP_OK;
 }

@@ -39,6 +39,9 @@ std::string tune_key(const hp_nest* nest);
 hp_status plan_for_batch(const hp_nest* nest, uint32_t flags, bool use_tuner, int nw, Lowered* out);
 
 // Build the nest and map a recipe stands for (false if the recipe does not apply).
-bool apply_recipe(const hp_nest* nest, const Recipe& r, int nw, hp_nest* shaped, hp_level_map* map);
+// *flat_block receives 0, or the block length when `shaped` is the aligned interior
+// of blocks that are not a multiple of the row length (see DevPlan::flat_b).
+bool apply_recipe(const hp_nest* nest, const Recipe& r, int nw, hp_nest* shaped, hp_level_map* map,
+                  int64_t* flat_block);
 
 }  // namespace hp

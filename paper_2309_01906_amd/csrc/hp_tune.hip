@@ -100,11 +100,14 @@ std::string tune_key(const hp_nest* n) {
   return buf;
 }
 
-bool apply_recipe(const hp_nest* n, const Recipe& r, int nw, hp_nest* shaped, hp_level_map* map) {
+bool apply_recipe(const hp_nest* n, const Recipe& r, int nw, hp_nest* shaped, hp_level_map* map,
+                  int64_t* flat_block) {
   int p;
   int64_t block;
+  *flat_block = 0;
   if (r.mode == 0 || !single_segment(n, &p, &block)) return false;
   const int op = n->op[p];
+  const int c = 16 / elem_bytes(n->dtype);
   memset(shaped, 0, sizeof *shaped);
   memset(map, 0, sizeof *map);
   shaped->dtype = n->dtype;
@@ -114,9 +117,18 @@ bool apply_recipe(const hp_nest* n, const Recipe& r, int nw, hp_nest* shaped, hp
     map->scopes[l] = HP_SCOPE_G;
   }
   if (r.mode == 1) {
-    if (r.k <= 0 || block % r.k != 0 || p + 2 > HP_MAX_DEPTH) return false;
+    if (r.k <= 0 || p + 2 > HP_MAX_DEPTH) return false;
     if (r.vj < 1 || r.vj > 64 || (r.vj & (r.vj - 1)) || r.gj < 1) return false;
-    shaped->extent[p] = block / r.k;
+    // rows of k elements; a block that is not a whole number of rows keeps its
+    // aligned interior of whole rows and spreads the rest over its threads
+    int64_t rows = block / r.k;
+    if (block % r.k != 0) {
+      if (r.k % c != 0) return false;
+      rows = flat_interior(block, c, r.k) / r.k;
+      if (rows < 1) return false;
+      *flat_block = block;
+    }
+    shaped->extent[p] = rows;
     shaped->op[p] = op;
     shaped->extent[p + 1] = r.k;
     shaped->op[p + 1] = op;
@@ -136,6 +148,10 @@ bool apply_recipe(const hp_nest* n, const Recipe& r, int nw, hp_nest* shaped, hp
     if (p < 1 || r.pw < 1 || r.pw > 64 || (r.pw & (r.pw - 1)) || r.opt < 1) return false;
     const int64_t eo = n->extent[p - 1];
     shaped->extent[p] = block;
+    if (block % c != 0 && flat_interior(block, c, c) >= c) {  // vector loads on the aligned interior
+      shaped->extent[p] = flat_interior(block, c, c);
+      *flat_block = block;
+    }
     shaped->op[p] = op;
     shaped->depth = p + 1;
     const int64_t parts = 64 / r.pw;
@@ -160,7 +176,9 @@ Recipe default_recipe(const hp_nest* n, int nw) {
   const int es = elem_bytes(n->dtype);
   const int64_t bytes = block * es;
   if (bytes >= (16 << 10)) return r;  // large blocks: the automatic map splits them
-  const int c = (block % (16 / es) == 0) ? 16 / es : 1;
+  // a block that is not a vector multiple is mapped as its aligned interior (vector
+  // loads) plus a few elements spread over its lanes
+  const int c = (block % (16 / es) == 0 || flat_interior(block, 16 / es, 16 / es) >= 16 / es) ? 16 / es : 1;
   int64_t lanes = (block + c - 1) / c;
   int pw = 1;
   while (pw < lanes && pw < 64) pw *= 2;
@@ -186,7 +204,8 @@ hp_status plan_for_batch(const hp_nest* nest, uint32_t flags, bool use_tuner, in
   }
   hp_nest shaped;
   hp_level_map m;
-  if (apply_recipe(nest, r, nw, &shaped, &m) && lower(&shaped, &m, flags, out, nw) == HP_OK) return HP_OK;
+  int64_t fb = 0;
+  if (apply_recipe(nest, r, nw, &shaped, &m, &fb) && lower(&shaped, &m, flags, out, nw, fb) == HP_OK) return HP_OK;
   return lower(nest, nullptr, flags, out, nw);
 }
 
@@ -312,8 +331,9 @@ extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t r
     hp_nest shaped;
     hp_level_map m;
     Lowered L;
-    if (!apply_recipe(nest, r, kBatchWaves, &shaped, &m)) return;
-    if (lower(&shaped, &m, flags, &L, kBatchWaves) != HP_OK) return;
+    int64_t fb = 0;
+    if (!apply_recipe(nest, r, kBatchWaves, &shaped, &m, &fb)) return;
+    if (lower(&shaped, &m, flags, &L, kBatchWaves, fb) != HP_OK) return;
     double us = 0;
     if (time_candidate_batch(L, R, in, in_stride, out, out_stride, reps, st, &us) != HP_OK) return;
     if (us < best.us * 0.98) {
@@ -330,7 +350,7 @@ extern "C" hp_status hp_tune_nest(const hp_nest* nest, uint32_t flags, int32_t r
     if (d.mode != 0) consider(d);
     // mode 1: (J, K) rows
     for (int64_t k = c; k <= block && k <= (int64_t)c * 1024; k *= 2) {
-      if (block % k != 0) continue;
+      if (block % k != 0 && flat_interior(block, c, k) < k) continue;
       for (int vj = 1; vj <= 16; vj *= 2) {
         if ((64 / vj) * c > 4 * k) continue;  // most lanes of a row would idle
         const int64_t J = block / k;

@@ -1,5 +1,6 @@
 """Helpers shared by the GPU tests: move seeded host inputs to the device, run the
 HIP path through the C ABI, and compare with the oracle."""
+import os
 import sys
 
 import numpy as np
@@ -8,6 +9,9 @@ import oracle
 import paper_2309_01906_amd as hp
 
 OPS = hp.OP_NAMES
+# the committed tuner cache the benchmark loads
+ROOT_TUNE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2309_01906_amd",
+                         "tune_gfx950.txt")
 
 
 def say(*a):

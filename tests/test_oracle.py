@@ -447,3 +447,23 @@ def test_stencil_matches_an_independent_evaluation():
         np.testing.assert_array_equal(oracle.stencil(x, steps, 0.6, 0.1), _np_jacobi(x, steps, 0.6, 0.1))
     tiny = workloads.normal_f32(121, (2, 9))  # no interior: unchanged
     np.testing.assert_array_equal(oracle.stencil(tiny, 4, 0.6, 0.1), tiny.astype(np.float64))
+
+
+def test_verify_helper_flags_planted_mistakes():
+    """oracle.verify (the many-nest checker of the GPU tests and the benchmark) passes
+    the oracle's own results and catches a wrong integer and a float beyond 1e-6."""
+    x = workloads.normal_f32(11, (8, 100))
+    xi = workloads.uniform_i32(12, (4, 50), -5, 5)
+    r = oracle.reduce(x, (8, 100), (0, 1), oracle.F32)
+    ri = oracle.reduce(xi, (4, 50), (0, 1), oracle.I32)
+    ok = oracle.verify([(x, (8, 100), (0, 1), oracle.F32, r), (xi, (4, 50), (0, 1), oracle.I32, ri)])
+    assert ok["ok"] and ok["nests"] == 2 and ok["float_outputs"] == 8 and ok["max_rel_err"] == 0.0
+    bad_i = ri.copy()
+    bad_i[3] += 1
+    v = oracle.verify([(xi, (4, 50), (0, 1), oracle.I32, bad_i)])
+    assert not v["ok"] and v["int_nests_mismatched"] == 1 and v["failures"] == [0]
+    bad_f = r.copy()
+    bad_f[5] += 3e-6 * max(abs(bad_f[5]), 1.0)
+    v = oracle.verify([(xi, (4, 50), (0, 1), oracle.I32, ri), (x, (8, 100), (0, 1), oracle.F32, bad_f)])
+    assert not v["ok"] and not v["float_within"] and v["failures"] == [1]
+    assert v["worst_condition_number"] >= 1.0

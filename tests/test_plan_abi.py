@@ -5,6 +5,7 @@ import itertools
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2309_01906_amd as hp
@@ -126,8 +127,12 @@ def test_output_types_match_the_oracle_rule():
 
 
 def test_scalar_chunk_when_extent_is_ragged():
+    # blocks too short to hold an aligned vector wherever they start: one element per load
     assert hp.inspect((4, 6), ("NONE", "SUM"), hp.F32)["chunk"] == 1
-    assert hp.inspect((4, 7), ("NONE", "SUM"), hp.F32)["chunk"] == 1
+    assert hp.inspect((4, 14), ("NONE", "SUM"), hp.BF16)["chunk"] == 1
+    assert hp.inspect((4, 6, 3), ("NONE", "MAX", "ARGMIN"), hp.I32)["chunk"] == 1
+    # long enough: flat blocks keep the 16-byte vector
+    assert hp.inspect((4, 7), ("NONE", "SUM"), hp.F32)["chunk"] == 4
     assert hp.inspect((4, 8), ("NONE", "SUM"), hp.BF16)["chunk"] == 8
     assert hp.inspect((4, 8), ("NONE", "SUM"), hp.F32, flags=hp.FLAG_SCALAR)["chunk"] == 1
 
@@ -212,3 +217,36 @@ def test_xcd_scope_planning():
         with pytest.raises(hp.HPError) as e:
             hp.inspect(ext, ops, dt, m, fl)
         assert e.value.status_name == status and words in str(e.value), (m, str(e.value))
+
+
+def test_flat_block_planning():
+    """A single SUM / MIN / MAX reduction whose block is not a multiple of the 16-byte
+    vector is planned as the aligned interior of each output's contiguous block (16-byte
+    loads) plus a rest spread over the output's threads; other nests keep their plans."""
+    cases = [((4096, 65537), ("NONE", "SUM"), hp.F32, 4), ((7, 3, 5, 7), ("NONE", "SUM", "SUM", "SUM"), hp.BF16, 8),
+             ((100, 101), ("NONE", "MAX"), hp.I32, 4), ((1, 1000003), ("SUM", "SUM"), hp.F32, 4),
+             ((3, 1001), ("NONE", "MIN"), hp.I32, 4), ((9, 2, 3, 5), ("NONE", "SUM", "SUM", "SUM"), hp.F32, 4)]
+    for ext, ops, dt, c in cases:
+        i = hp.inspect(ext, ops, dt)
+        p = next(k for k, o in enumerate(ops) if o != "NONE")
+        block = int(np.prod(ext[p:]))
+        assert i["flat_block"] == block, (ext, i)
+        assert i["in_elems"] == int(np.prod(ext)) and i["chunk"] == c
+        assert i["depth"] == p + 1  # the interior view: one reducing level
+    # the interior of a long row is whole strips: the stream stays unmasked
+    i = hp.inspect((4096, 65537), ("NONE", "SUM"), hp.F32)
+    span = i["units"][1][1] * i["units"][1][2] * 4
+    assert i["strips"][1] * span <= 65537 - 3 and i["kernel_name"] == "hp::k_nest_f32_lean<4>"
+    # not flat: several segments, ARG, an explicit map, the scalar flag, blocks too short
+    for ext, ops, dt, m, fl in [((64, 128, 64, 63), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32, None, 0),
+                                ((10, 1001), ("NONE", "ARGMIN"), hp.I32, None, 0),
+                                ((10, 1001), ("NONE", "SUM"), hp.F32, ["G", "V"], 0),
+                                ((10, 1001), ("NONE", "SUM"), hp.F32, None, hp.FLAG_SCALAR),
+                                ((10, 14), ("NONE", "SUM"), hp.BF16, None, 0),
+                                ((10, 1024), ("NONE", "SUM"), hp.F32, None, 0)]:
+        i = hp.inspect(ext, ops, dt, m, fl)
+        assert i["flat_block"] == 0, (ext, ops, m, fl)
+    # batched plans (default recipes and the committed tuner cache) use flat blocks too
+    nests = [((8, 3, 333), ("NONE", "SUM", "SUM"), hp.BF16), ((1, 5, 4099), ("NONE", "SUM", "SUM"), hp.BF16)]
+    infos = hp.batch_inspect(nests)
+    assert all(x["flat_block"] == int(np.prod(n[0][1:])) for x, n in zip(infos, nests)), infos

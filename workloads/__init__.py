@@ -12,7 +12,7 @@ Workloads (seeds are ``BASE_SEED + n`` for workload n):
 * ``c3``: 4-level nest, int32 64x128x64x64 uniform in [0, 2^20),
   out[i] = sum_j max_k argmin_l.
 * ``c4``: 10,000 bf16 nests of log-normal total length (median 4096,
-  max 2^22), 3 levels (e0, j, k), all reduced levels SUM.
+  max 2^22), 3 levels (e0, j, k) with j k = ceil(L / e0), reduced levels SUM.
 * ``c5``: open-loop Poisson request stream (20k req/s), 2-4 level nests of
   log-normal byte size (median 64 KiB, max 256 MiB), half int32, half fp32.
 """
@@ -180,8 +180,10 @@ class BatchWorkload:
 
 def c4_batch(n: int = 10000, median: int = 4096, maximum: int = 1 << 22, seed: int = BASE_SEED + 4) -> BatchWorkload:
     """Uneven bf16 nests.  Total length L ~ LogNormal(ln median, sigma) clipped to
-    [64, maximum]; e0 = 2^U with U uniform in {0..min(6, log2(L/64))};
-    reduced length I = 64*ceil(L / (64 e0)); shape (e0, I/64, 64)."""
+    [64, maximum]; e0 = 2^U with U uniform in {0..min(6, log2(L/64))}; reduced
+    length I = ceil(L / e0), any integer; shape (e0, j, k) with k = gcd(I, 64) and
+    j = I / k.  (How the reduced block meets the hardware is the planner's and the
+    tuner's choice: a single reduction may be reshaped.)"""
     sigma = lognormal_sigma(median, maximum, n)
     z = normal_f64(seed, n, start=0)
     u = unit_f64(seed ^ 0x5DEECE66D, n)
@@ -193,8 +195,9 @@ def c4_batch(n: int = 10000, median: int = 4096, maximum: int = 1 << 22, seed: i
         umax = min(6, int(math.floor(math.log2(L / 64)))) if L >= 64 else 0
         U = int(u[i] * (umax + 1))
         e0 = 1 << U
-        I = 64 * ((L + 64 * e0 - 1) // (64 * e0))
-        nests.append(Nest((e0, I // 64, 64), (NONE, SUM, SUM), BF16))
+        I = (L + e0 - 1) // e0
+        k = math.gcd(I, 64)
+        nests.append(Nest((e0, I // k, k), (NONE, SUM, SUM), BF16))
         offsets[i] = off
         off += ((e0 * I + 7) // 8) * 8
     return BatchWorkload(nests, offsets, off, seed + 1000)
