@@ -352,5 +352,8 @@ def test_flat_blocks(ext, op, kind):
         x = workloads.uniform_i32(83, ext, -(2**31), 2**31 - 1)
     say("case flat", ext, op, kind)
     got, info = gpu_reduce(x, ext, ops)
-    assert info["flat_block"] == int(np.prod(ext[1:] if ops[0] == "NONE" else ext)), info
+    b = int(np.prod(ext[1:] if ops[0] == "NONE" else ext))
+    c = 8 if kind == "bf16" else 4
+    # a block shorter than 2c - 1 elements may hold no aligned vector: plain path
+    assert info["flat_block"] == (b if b >= 2 * c - 1 else 0), info
     assert_match(got, x, ext, ops, what=f"flat {ext} {op} {kind}")
