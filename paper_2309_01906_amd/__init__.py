@@ -141,7 +141,7 @@ def kernel_name(inf: PlanInfo) -> str:
         return f"hp::k_nest_i32_{kind}<{c}>"
     t = "bf16" if inf.in_bytes == 2 * inf.in_elems else "f32"
     if inf.kernel == KERNEL_LEAN:
-        return f"hp::k_nest_{t}_lean<{c}>"
+        return f"hp::k_nest_{t}_lean{'_flat' if inf.flat_block else ''}<{c}>"
     return f"hp::k_nest_{t}<{c}, {4 if inf.kernel == KERNEL_GENERIC4 else MAX_DEPTH}>"
 
 

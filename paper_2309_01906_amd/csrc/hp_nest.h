@@ -597,7 +597,9 @@ __device__ __forceinline__ typename T::Acc flat_rest(const DevPlan& P, const typ
 
 // Reduce the current output's block; returns segment P.gq's value (the output, or
 // this workgroup's partial of it when that segment spans workgroups).
-template <class T, int C, int NS, int U, int KD, bool LEAN, bool PF = true>
+// FL: flat-block plans may run this instantiation (the rest-element code is
+// compiled in); kernels that never see them leave it out and keep fewer registers.
+template <class T, int C, int NS, int U, int KD, bool LEAN, bool PF = true, bool FL = true>
 __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                                         long long base, bool vnone, const Thread<KD>& th, char* lds,
                                                         long long flat_s = 0) {
@@ -648,7 +650,8 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
   auto consume = [&](Acc ai) {
     // flat blocks have one segment walked in one outer iteration: the rest of the
     // block joins the lane partials before they are combined
-    if (P.flat_b && vnone) ai = flat_rest<T, KD>(P, in, flat_s, ai, th);
+    if constexpr (FL)
+      if (P.flat_b && vnone) ai = flat_rest<T, KD>(P, in, flat_s, ai, th);
     ai = combine_seg<T, KD>(P, P.seg[inner], ai, th, lds);
     if (inner == stop) {
       fin = ai;
@@ -825,7 +828,8 @@ __device__ __forceinline__ DPair dpair_merge(DPair a, DPair b) {
 // ---------------------------------------------------------------------------
 // one workgroup
 
-template <class T, int C, int NS, int U, int KD, bool LEAN = false, bool WAVE = false, bool PF = true>
+template <class T, int C, int NS, int U, int KD, bool LEAN = false, bool WAVE = false, bool PF = true,
+          bool FL = true>
 __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* __restrict__ in,
                                        void* __restrict__ out, unsigned char* __restrict__ ws, uint32_t g,
                                        char* lds) {
@@ -892,9 +896,9 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
       }
     } else {
       // flat blocks: the aligned interior starts h elements into the block
-      const long long h = P.flat_b ? ((-off) & (long long)(P.chunk - 1)) : 0;
+      const long long h = (FL && P.flat_b) ? ((-off) & (long long)(P.chunk - 1)) : 0;
       const typename T::Acc a =
-          reduce_block<T, C, NS, U, KD, LEAN, PF>(P, in, off + h + base_red, vnone, th, lds, off);
+          reduce_block<T, C, NS, U, KD, LEAN, PF, FL>(P, in, off + h + base_red, vnone, th, lds, off);
       if (P.gmode == GCOMB_NONE) {
         if (vnone && red_writer) {
           if constexpr (T::kFloat) store_flt(P, out, o, (double)a.s + (double)a.c);

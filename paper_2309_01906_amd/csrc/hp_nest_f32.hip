@@ -20,6 +20,16 @@ k_nest_f32_lean(const DevPlan* __restrict__ Pd, const float* __restrict__ in, vo
                unsigned char* __restrict__ ws) {
   extern __shared__ __align__(16) char lds[];
   const DevPlan& P = *Pd;
+  wg_run<FloatT<float>, C, 1, 4, 4, true, false, true, false>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+}
+
+// The same for flat-block plans (blocks that are not a multiple of the vector).
+template <int C>
+__global__ void __launch_bounds__(512)
+k_nest_f32_lean_flat(const DevPlan* __restrict__ Pd, const float* __restrict__ in, void* __restrict__ out,
+               unsigned char* __restrict__ ws) {
+  extern __shared__ __align__(16) char lds[];
+  const DevPlan& P = *Pd;
   wg_run<FloatT<float>, C, 1, 4, 4, true>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
 }
 
@@ -28,7 +38,8 @@ hp_status launch_nest_f32(const DevPlan& P, const DevPlan* dP, const void* in, v
   const float* x = reinterpret_cast<const float*>(in);
   unsigned char* w = reinterpret_cast<unsigned char*>(ws);
   if (P.kernel == HP_KERNEL_LEAN) {
-    hipLaunchKernelGGL(k_nest_f32_lean<4>, grid, block, lds, st, dP, x, out, w);
+    if (P.flat_b) hipLaunchKernelGGL(k_nest_f32_lean_flat<4>, grid, block, lds, st, dP, x, out, w);
+    else hipLaunchKernelGGL(k_nest_f32_lean<4>, grid, block, lds, st, dP, x, out, w);
   } else if (P.kernel == HP_KERNEL_GENERIC4) {
     if (P.chunk == 4) hipLaunchKernelGGL((k_nest_f32<4, 4>), grid, block, lds, st, dP, x, out, w);
     else hipLaunchKernelGGL((k_nest_f32<1, 4>), grid, block, lds, st, dP, x, out, w);

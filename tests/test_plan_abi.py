@@ -236,7 +236,7 @@ def test_flat_block_planning():
     # the interior of a long row is whole strips: the stream stays unmasked
     i = hp.inspect((4096, 65537), ("NONE", "SUM"), hp.F32)
     span = i["units"][1][1] * i["units"][1][2] * 4
-    assert i["strips"][1] * span <= 65537 - 3 and i["kernel_name"] == "hp::k_nest_f32_lean<4>"
+    assert i["strips"][1] * span <= 65537 - 3 and i["kernel_name"] == "hp::k_nest_f32_lean_flat<4>"
     # not flat: several segments, ARG, an explicit map, the scalar flag, blocks too short
     for ext, ops, dt, m, fl in [((64, 128, 64, 63), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32, None, 0),
                                 ((10, 1001), ("NONE", "ARGMIN"), hp.I32, None, 0),
