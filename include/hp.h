@@ -202,6 +202,27 @@ hp_status hp_run(hp_plan_t plan, const void* d_in, void* d_out, void* stream);
  * sure no launch using the plan is still running. */
 hp_status hp_destroy(hp_plan_t plan);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, hosts that forbid hipMalloc): hp_plan followed by hp_run
+ * and hp_destroy in one call that allocates nothing.  The nest is planned on the
+ * host exactly as hp_plan would plan it (same kernels, same bits as hp_run); the
+ * plan, the fold tasks and the workgroup partials of a grid-split nest go into a
+ * file-scope device array of HP_STATIC_SCRATCH_BYTES bytes that each GPU the
+ * library runs on holds until the process ends.  The plan reaches that array
+ * through a small install kernel on `stream`, then the nest kernels run there.
+ * d_in, d_out and stream are as for hp_run; the call is asynchronous.
+ * Every call on one GPU shares that GPU's array: calls on one stream are ordered,
+ * but calls that overlap on one GPU (two streams, two threads) race and may give
+ * wrong results.  Nothing in the array needs clearing: every run writes what it
+ * reads.
+ * Errors: as hp_plan_inspect for the nest and map; HP_EINVAL for null or
+ * misaligned pointers; HP_ETOOBIG when the nest needs more workspace or fold
+ * tasks than the array holds (about 7 MiB of partials, 65536 fold tasks);
+ * HP_EDEVICE for launch failures. */
+#define HP_STATIC_SCRATCH_BYTES (8u << 20)
+hp_status hp_reduce_static(const hp_nest* nest, const hp_level_map* map, uint32_t flags, const void* d_in,
+                           void* d_out, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many nests of uneven sizes in one persistent launch per kernel family.
  * Nests are planned as one-wavefront plans, and every wavefront of the persistent

@@ -86,6 +86,8 @@ def lib():
         L.hp_status_str.restype = ctypes.c_char_p
         L.hp_stream_read.argtypes = [vp, ctypes.c_size_t, vp, ctypes.c_int32, vp]
         L.hp_stream_read.restype = st
+        L.hp_reduce_static.argtypes = [ctypes.POINTER(Nest), ctypes.POINTER(LevelMap), ctypes.c_uint32, vp, vp, vp]
+        L.hp_reduce_static.restype = st
         _lib = L
     return _lib
 
@@ -321,6 +323,20 @@ def reduce(inp, extents, ops, level_map=None, flags: int = 0, stream=None):
     out = p.run(inp, stream=stream)
     _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     p.close()
+    return out
+
+
+def reduce_static(inp, out, extents, ops, level_map=None, flags: int = 0, stream=None):
+    """hp_reduce_static: plan and run into ``out`` without allocating device memory
+    (the library's static scratch holds the plan and partials).  Asynchronous on
+    ``stream``; calls that overlap on one GPU race."""
+    n = make_nest(extents, ops, dtype_of(inp))
+    m = make_map(level_map)
+    if not (inp.is_cuda and out.is_cuda and inp.is_contiguous() and out.is_contiguous()):
+        raise ValueError("input and output must be contiguous device tensors")
+    check(lib().hp_reduce_static(ctypes.byref(n), ctypes.byref(m) if m is not None else None, flags,
+                                 ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 _stream_handle(stream)))
     return out
 
 

@@ -250,3 +250,18 @@ def test_flat_block_planning():
     nests = [((8, 3, 333), ("NONE", "SUM", "SUM"), hp.BF16), ((1, 5, 4099), ("NONE", "SUM", "SUM"), hp.BF16)]
     infos = hp.batch_inspect(nests)
     assert all(x["flat_block"] == int(np.prod(n[0][1:])) for x, n in zip(infos, nests)), infos
+
+
+def test_static_entry_host_errors():
+    """hp_reduce_static rejects bad pointers and over-size nests before touching a device."""
+    import ctypes
+    L = hp.lib()
+    n = hp.make_nest((8192, 1024), (0, 1), hp.F32)
+    m = hp.make_map(["G", ("G", {"G": 64})])  # 8192 outputs x 64 partials x 16 B = 8 MiB of partials
+    assert L.hp_reduce_static(ctypes.byref(n), ctypes.byref(m), 0, 4096, 4096, None) == 6  # HP_ETOOBIG
+    assert b"static scratch" in L.hp_last_error()
+    assert L.hp_reduce_static(ctypes.byref(n), None, 0, None, 4096, None) == 1  # null input
+    assert L.hp_reduce_static(ctypes.byref(n), None, 0, 4100, 4096, None) == 1  # misaligned input
+    assert L.hp_reduce_static(ctypes.byref(n), None, 0, 4096, 4100, None) == 1  # misaligned fp64 output
+    bad = hp.make_nest((4, 0), (0, 1), hp.F32)
+    assert L.hp_reduce_static(ctypes.byref(bad), None, 0, 4096, 4096, None) == 1  # extent < 1
