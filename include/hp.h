@@ -162,7 +162,9 @@ typedef enum hp_kernel {
   HP_KERNEL_INT_FLAT = 3, /* int32, depth <= 4, one reducing segment */
   HP_KERNEL_INT_SEG = 4,  /* int32, depth <= 4, up to three segments */
   HP_KERNEL_INT_DEEP = 5, /* int32, anything else */
-  HP_KERNEL_ORDERED = 6   /* ordered products of AFFINE64 / MAT2X2_64 elements */
+  HP_KERNEL_ORDERED = 6,  /* ordered products of AFFINE64 / MAT2X2_64 elements */
+  HP_KERNEL_INT_CHAIN = 7 /* int32, two or three reducing levels with one operator each, every level
+                             divided evenly by its units, innermost levels on lanes (the chain kernel) */
 } hp_kernel;
 
 typedef struct hp_plan_s* hp_plan_t;

@@ -130,14 +130,19 @@ def make_map(level_map) -> LevelMap | None:
     return m
 
 
-KERNEL_LEAN, KERNEL_GENERIC4, KERNEL_GENERIC8, KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP, KERNEL_ORDERED = range(7)
+(KERNEL_LEAN, KERNEL_GENERIC4, KERNEL_GENERIC8, KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP, KERNEL_ORDERED,
+ KERNEL_INT_CHAIN) = range(8)
+OP_TEMPLATE = {SUM: "1", MIN: "2", MAX: "3", ARGMIN: "4", ARGMAX: "5"}
 
 
-def kernel_name(inf: PlanInfo) -> str:
-    """Symbol of the kernel hp_run launches for a plan (as profilers print it)."""
+def kernel_name(inf: PlanInfo, ops=None) -> str:
+    """Symbol of the kernel hp_run launches for a plan (as profilers print it); the chain
+    kernel's first template argument is the innermost operator (from ``ops``)."""
     c = inf.chunk
     if inf.kernel == KERNEL_ORDERED:
         return "hp::k_ordered<2, 8>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 8>"
+    if inf.kernel == KERNEL_INT_CHAIN:
+        return f"hp::k_nest_i32_chain<{OP_TEMPLATE[_op(ops[-1])] if ops else '?'}, {inf.nseg}>"
     if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP):
         kind = {KERNEL_INT_FLAT: "flat", KERNEL_INT_SEG: "seg", KERNEL_INT_DEEP: "deep"}[inf.kernel]
         return f"hp::k_nest_i32_{kind}<{c}>"
@@ -147,14 +152,14 @@ def kernel_name(inf: PlanInfo) -> str:
     return f"hp::k_nest_{t}<{c}, {4 if inf.kernel == KERNEL_GENERIC4 else MAX_DEPTH}>"
 
 
-def _info_dict(inf: PlanInfo) -> dict:
+def _info_dict(inf: PlanInfo, ops=None) -> dict:
     d = inf.depth
     names = "GWVL"
     return {
         "depth": d, "out_dtype": inf.out_dtype, "n_out": inf.n_out, "out_bytes": inf.out_bytes,
         "in_elems": inf.in_elems, "in_bytes": inf.in_bytes, "grid": inf.grid, "waves": inf.waves,
         "chunk": inf.chunk, "gsplit": inf.gsplit, "workspace_bytes": inf.workspace_bytes,
-        "lds_bytes": inf.lds_bytes, "nseg": inf.nseg, "kernel": inf.kernel, "kernel_name": kernel_name(inf),
+        "lds_bytes": inf.lds_bytes, "nseg": inf.nseg, "kernel": inf.kernel, "kernel_name": kernel_name(inf, ops),
         # a level on X reports "X" in place of the G it lowers to
         "map": [("X" if inf.scopes[i] & 16 else "") +
                 "".join(names[b] for b in range(4) if inf.scopes[i] >> b & 1 and not (b == 0 and inf.scopes[i] & 16))
@@ -172,7 +177,7 @@ def inspect(extents, ops, dtype, level_map=None, flags: int = 0) -> dict:
     inf = PlanInfo()
     check(lib().hp_plan_inspect(ctypes.byref(n), ctypes.byref(m) if m is not None else None,
                                 flags, ctypes.byref(inf)))
-    return _info_dict(inf)
+    return _info_dict(inf, ops)
 
 
 def _torch():
@@ -218,7 +223,7 @@ class Plan:
                             ctypes.byref(self._h)))
         inf = PlanInfo()
         check(lib().hp_plan_info_get(self._h, ctypes.byref(inf)))
-        self.info = _info_dict(inf)
+        self.info = _info_dict(inf, self.ops)
 
     def _out_shape(self):
         w = WIDTH.get(self.info["out_dtype"])
@@ -384,7 +389,7 @@ def batch_inspect(nests, flags: int = 0):
         arr[i] = make_nest(ext, ops, dt)
     infos = (PlanInfo * len(nests))()
     check(lib().hp_batch_plan_inspect(arr, len(nests), flags, infos))
-    return [_info_dict(infos[i]) for i in range(len(nests))]
+    return [_info_dict(infos[i], nests[i][1]) for i in range(len(nests))]
 
 
 class Batch:
@@ -397,12 +402,13 @@ class Batch:
             arr[i] = make_nest(ext, ops, dt)
         self._h = ctypes.c_void_p()
         self.n = len(nests)
+        self._ops = [ops for _, ops, _ in nests]
         check(lib().hp_batch_plan(arr, self.n, flags, ctypes.byref(self._h)))
 
     def info(self, i: int) -> dict:
         inf = PlanInfo()
         check(lib().hp_batch_info(self._h, i, ctypes.byref(inf)))
-        return _info_dict(inf)
+        return _info_dict(inf, self._ops[i])
 
     def stats(self):
         a, b, w, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()

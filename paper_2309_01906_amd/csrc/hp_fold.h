@@ -25,12 +25,24 @@ namespace hp {
 //     spanning segments are folded by one lane, digits in index order.
 constexpr long long kSeqFold = 16;
 
+// Partials are read kFoldBatch at a time, all loads issued before the first is
+// used, so a fold of up to kFoldBatch partials waits for memory once rather than
+// once per partial; the order of the additions is unchanged.
+constexpr int kFoldBatch = 16;
+
 __device__ __forceinline__ double fold_flt_seq(const char* part, long long G) {
   DPair a{0.0, 0.0};
-  for (long long k = 0; k < G; ++k) {
-    const FAcc v = FloatT<float>::get(part, k);
-    dpair_add(a, (double)v.s);
-    dpair_add(a, (double)v.c);
+  for (long long k0 = 0; k0 < G; k0 += kFoldBatch) {
+    FAcc v[kFoldBatch];
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u)
+      if (k0 + u < G) v[u] = FloatT<float>::get(part, k0 + u);
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u)
+      if (k0 + u < G) {
+        dpair_add(a, (double)v[u].s);
+        dpair_add(a, (double)v[u].c);
+      }
   }
   return a.s + a.c;
 }
@@ -53,7 +65,15 @@ __device__ __forceinline__ double fold_flt_wave(const char* part, long long G, i
 
 __device__ __forceinline__ long long fold_int_uniform_seq(const char* part, long long G, int op) {
   IAcc a = IntT::identity(op);
-  for (long long k = 0; k < G; ++k) a = IntT::merge(a, IntT::get(part, k), op);
+  for (long long k0 = 0; k0 < G; k0 += kFoldBatch) {
+    IAcc v[kFoldBatch];
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u)
+      if (k0 + u < G) v[u] = IntT::get(part, k0 + u);
+#pragma unroll
+    for (int u = 0; u < kFoldBatch; ++u)
+      if (k0 + u < G) a = IntT::merge(a, v[u], op);
+  }
   return IntT::emit(a, op);
 }
 

@@ -57,7 +57,8 @@ struct DevSeg {
   uint32_t lds_lanes;    // lane bits that belong to levels outside the segment
   int32_t nwu;           // wave units combined by the segment (2^popcount(wmask))
   uint32_t gunits;       // product of the G units of the segment's levels
-  int32_t pad;
+  uint32_t ufast;        // lane bits b of vmask whose butterfly step may take a mirror or
+                         // permlane-swap partner: every lower lane bit is already reduced
 };
 
 struct alignas(16) DevPlan {

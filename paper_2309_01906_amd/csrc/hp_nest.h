@@ -13,9 +13,9 @@
 //     done its partials are combined and fed to the enclosing level's operator.
 // Combines follow the paper's recursive reduction (section 2: every level collects
 // its siblings' results through its cheapest means):
-//   lanes       xor butterfly: DPP quad_perm / row_shr / row_shl, ds_swizzle and
-//               ds_bpermute (section 3.7's shuffle; a wave64 runs in lockstep, so no
-//               masks or warp syncs are needed);
+//   lanes       xor butterfly: DPP quad_perm / mirrors / row shifts and gfx950's
+//               permlane16 / permlane32 swaps (hp_lanes.h; section 3.7's shuffle; a
+//               wave64 runs in lockstep, so no masks or warp syncs are needed);
 //   waves       one LDS slot per wave, s_barrier, every wave folds its group's slots
 //               in wave order (section 3.7's fallback through memory one level up);
 //   workgroups  a partial per workgroup in global memory; a second, small kernel
@@ -32,6 +32,7 @@
 #include <type_traits>
 
 #include "hp_internal.h"
+#include "hp_lanes.h"
 
 namespace hp {
 
@@ -98,7 +99,11 @@ struct FloatT {
   using Raw = RawT;
   using Acc = FAcc;
   static constexpr bool kFloat = true;
+  static constexpr bool kKey = false;
   __device__ static __forceinline__ Acc identity(int) { return Acc{0.f, 0.f}; }
+  // TwoSum per element, its exact error added to c.  (Kahan's four-operation step
+  // rounds x + c before it adds, which loses about u |x| per element: on a 2^20-element
+  // sum of N(0,1) values that is 2e-6 relative to the result, above the 1e-6 rule.)
   __device__ static __forceinline__ void add(Acc& a, float x, long long, int) {
     float s, e;
     two_sum(a.s, x, s, e);
@@ -132,6 +137,7 @@ struct IntT {
   using Raw = int32_t;
   using Acc = IAcc;
   static constexpr bool kFloat = false;
+  static constexpr bool kKey = false;
   __device__ static __forceinline__ Acc identity(int op) {
     switch (op) {
       case HP_OP_MIN: return Acc{0x7FFFFFFFFFFFFFFFll, 0, 0};
@@ -180,6 +186,59 @@ struct IntT {
   __device__ static __forceinline__ Acc get(const char* base, long long slot) {
     const long long* q = reinterpret_cast<const long long*>(base + slot * kSlotBytes);
     return Acc{q[0], (int)q[1], 0};
+  }
+};
+
+// Integer carrier as one 64-bit key, for plans in which every ARG level sees 32-bit
+// child values (the input, MIN / MAX of them, or an ARG level's index):
+//   SUM        the int64 sum (wrapping);
+//   MIN / MAX  the value;
+//   ARGMIN     value << 32 | t;  ARGMAX  value << 32 | (2^32 - 1 - t).
+// A signed 64-bit comparison of two ARG keys is the lexicographic order of (value,
+// index) with ties to the smaller index, so every merge is a 64-bit add, min or max
+// and butterfly steps move two words where the (value, index) pair moves three.
+// Grid partials are written in IntT's (value, index) form, which the fold reads.
+struct IntK {
+  using Raw = int32_t;
+  using Acc = long long;
+  static constexpr bool kFloat = false;
+  static constexpr bool kKey = true;
+  __device__ static __forceinline__ bool minlike(int op) { return op == HP_OP_MIN || op == HP_OP_ARGMIN; }
+  __device__ static __forceinline__ bool arg(int op) { return op == HP_OP_ARGMIN || op == HP_OP_ARGMAX; }
+  __device__ static __forceinline__ Acc identity(int op) {
+    if (op == HP_OP_MIN || op == HP_OP_ARGMIN) return 0x7FFFFFFFFFFFFFFFll;
+    if (op == HP_OP_MAX || op == HP_OP_ARGMAX) return (long long)0x8000000000000000ull;
+    return 0;
+  }
+  __device__ static __forceinline__ Acc key(long long x, long long t, int op) {
+    const unsigned long long hi = (unsigned long long)(uint32_t)(int32_t)x << 32;
+    if (op == HP_OP_ARGMIN) return (long long)(hi | (uint32_t)t);
+    if (op == HP_OP_ARGMAX) return (long long)(hi | (0xFFFFFFFFu - (uint32_t)t));
+    return x;
+  }
+  __device__ static __forceinline__ Acc merge(Acc a, Acc b, int op) {
+    if (op == HP_OP_SUM) return (long long)((unsigned long long)a + (unsigned long long)b);
+    if (op == HP_OP_NONE) return a;
+    return minlike(op) ? (b < a ? b : a) : (b > a ? b : a);
+  }
+  __device__ static __forceinline__ void add(Acc& a, long long x, long long t, int op) { a = merge(a, key(x, t, op), op); }
+  __device__ static __forceinline__ long long emit(Acc a, int op) {
+    if (op == HP_OP_ARGMIN) return (long long)(uint32_t)a;
+    if (op == HP_OP_ARGMAX) return (long long)(0xFFFFFFFFu - (uint32_t)a);
+    return a;
+  }
+  // LDS slots hold the key itself
+  __device__ static __forceinline__ void put(char* base, long long slot, Acc a) {
+    *reinterpret_cast<long long*>(base + slot * kSlotBytes) = a;
+  }
+  __device__ static __forceinline__ Acc get(const char* base, long long slot) {
+    return *reinterpret_cast<const long long*>(base + slot * kSlotBytes);
+  }
+  // grid partials in the (value, index) form of IntT
+  __device__ static __forceinline__ void put_partial(char* base, long long slot, Acc a, int op) {
+    long long* q = reinterpret_cast<long long*>(base + slot * kSlotBytes);
+    q[0] = arg(op) ? (long long)(int32_t)(uint32_t)((unsigned long long)a >> 32) : a;
+    q[1] = arg(op) ? emit(a, op) : 0;
   }
 };
 
@@ -295,6 +354,31 @@ template <int OP>
 struct AddChunk<IntT, 1, OP> {
   __device__ static __forceinline__ void run(IAcc& a, int x, long long t, bool ok) {
     IntT::add(a, masked_i<OP>(x, ok), t, OP);
+  }
+};
+// Key carriers: the four elements are reduced in 32 bits (for ARG the first
+// position of the extreme value), then merged into the key once.
+template <int OP>
+struct AddChunk<IntK, 4, OP> {
+  __device__ static __forceinline__ void run(long long& a, i32x4 x, long long t, bool ok) {
+    const int x0 = masked_i<OP>(x.x, ok), x1 = masked_i<OP>(x.y, ok);
+    const int x2 = masked_i<OP>(x.z, ok), x3 = masked_i<OP>(x.w, ok);
+    if constexpr (OP == HP_OP_SUM) {
+      a = (long long)((unsigned long long)a + (unsigned long long)((long long)x0 + x1) +
+                      (unsigned long long)((long long)x2 + x3));
+    } else {
+      constexpr bool mn = OP == HP_OP_MIN || OP == HP_OP_ARGMIN;
+      const int m = mn ? min(min(x0, x1), min(x2, x3)) : max(max(x0, x1), max(x2, x3));
+      int pos = 0;
+      if constexpr (OP == HP_OP_ARGMIN || OP == HP_OP_ARGMAX) pos = x0 == m ? 0 : x1 == m ? 1 : x2 == m ? 2 : 3;
+      IntK::add(a, m, t + pos, OP);
+    }
+  }
+};
+template <int OP>
+struct AddChunk<IntK, 1, OP> {
+  __device__ static __forceinline__ void run(long long& a, int x, long long t, bool ok) {
+    IntK::add(a, masked_i<OP>(x, ok), t, OP);
   }
 };
 
@@ -507,19 +591,23 @@ struct InnerStream<FloatT<R>, C, U, KD, LEAN> {
     return stream_any<FloatT<R>, C, HP_OP_SUM, U, KD, LEAN>(P, in, base, valid, th);
   }
 };
-template <int C, int U, int KD, bool LEAN>
-struct InnerStream<IntT, C, U, KD, LEAN> {
-  __device__ static __forceinline__ IAcc run(const DevPlan& P, const int32_t* __restrict__ in, long long base,
-                                             bool valid, const Thread<KD>& th) {
+template <class I, int C, int U, int KD, bool LEAN>
+struct IntInnerStream {
+  __device__ static __forceinline__ typename I::Acc run(const DevPlan& P, const int32_t* __restrict__ in,
+                                                        long long base, bool valid, const Thread<KD>& th) {
     switch (P.seg[P.nseg - 1].op) {
-      case HP_OP_MIN: return stream_any<IntT, C, HP_OP_MIN, U, KD, LEAN>(P, in, base, valid, th);
-      case HP_OP_MAX: return stream_any<IntT, C, HP_OP_MAX, U, KD, LEAN>(P, in, base, valid, th);
-      case HP_OP_ARGMIN: return stream_any<IntT, C, HP_OP_ARGMIN, U, KD, LEAN>(P, in, base, valid, th);
-      case HP_OP_ARGMAX: return stream_any<IntT, C, HP_OP_ARGMAX, U, KD, LEAN>(P, in, base, valid, th);
-      default: return stream_any<IntT, C, HP_OP_SUM, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_MIN: return stream_any<I, C, HP_OP_MIN, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_MAX: return stream_any<I, C, HP_OP_MAX, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_ARGMIN: return stream_any<I, C, HP_OP_ARGMIN, U, KD, LEAN>(P, in, base, valid, th);
+      case HP_OP_ARGMAX: return stream_any<I, C, HP_OP_ARGMAX, U, KD, LEAN>(P, in, base, valid, th);
+      default: return stream_any<I, C, HP_OP_SUM, U, KD, LEAN>(P, in, base, valid, th);
     }
   }
 };
+template <int C, int U, int KD, bool LEAN>
+struct InnerStream<IntT, C, U, KD, LEAN> : IntInnerStream<IntT, C, U, KD, LEAN> {};
+template <int C, int U, int KD, bool LEAN>
+struct InnerStream<IntK, C, U, KD, LEAN> : IntInnerStream<IntK, C, U, KD, LEAN> {};
 
 // Synchronise the threads that run one task: the whole workgroup, or (for wave
 // tasks) one wavefront, which runs in lockstep and only needs its LDS accesses
@@ -533,14 +621,119 @@ __device__ __forceinline__ void group_sync(bool wave) {
   }
 }
 
+// One butterfly step on lane bit B for a carrier of float pairs or integer keys
+// (moves from hp_lanes.h; `uni`: the step may take the mirror / permlane-swap form).
+template <int B>
+__device__ __forceinline__ FAcc lane_step(FAcc a, bool uni, int lane, int) {
+  if constexpr (B >= 4) {
+    if (uni) {
+      int s0, s1, c0, c1;
+      sides32<B>(__float_as_int(a.s), s0, s1);
+      sides32<B>(__float_as_int(a.c), c0, c1);
+      return FloatT<float>::merge(FAcc{__int_as_float(s0), __int_as_float(c0)},
+                                  FAcc{__int_as_float(s1), __int_as_float(c1)}, 0);
+    }
+  }
+  const FAcc o{__int_as_float(partner32<B>(__float_as_int(a.s), uni, lane)),
+               __int_as_float(partner32<B>(__float_as_int(a.c), uni, lane))};
+  return FloatT<float>::merge(a, o, 0);
+}
+
+// 64-bit integer sum step
+template <int B>
+__device__ __forceinline__ long long key_sum_step(long long a, bool uni, int lane) {
+  const int lo = (int)(uint32_t)(unsigned long long)a, hi = (int)(uint32_t)((unsigned long long)a >> 32);
+  if constexpr (B >= 4) {
+    if (uni) {
+      int l0, l1, h0, h1;
+      sides32<B>(lo, l0, l1);
+      sides32<B>(hi, h0, h1);
+      const unsigned long long x = ((unsigned long long)(uint32_t)h0 << 32) | (uint32_t)l0;
+      const unsigned long long y = ((unsigned long long)(uint32_t)h1 << 32) | (uint32_t)l1;
+      return (long long)(x + y);
+    }
+  }
+  const unsigned long long y = ((unsigned long long)(uint32_t)partner32<B>(hi, uni, lane) << 32) |
+                               (uint32_t)partner32<B>(lo, uni, lane);
+  return (long long)((unsigned long long)a + y);
+}
+
+// 32-bit min / max step (signed or unsigned)
+template <int B, bool MN, class W>
+__device__ __forceinline__ W word_step(W v, bool uni, int lane) {
+  if constexpr (B >= 4) {
+    if (uni) {
+      int x0, x1;
+      sides32<B>((int)v, x0, x1);
+      return MN ? min((W)x0, (W)x1) : max((W)x0, (W)x1);
+    }
+  }
+  const W o = (W)partner32<B>((int)v, uni, lane);
+  return MN ? min(v, o) : max(v, o);
+}
+
+template <bool MN, class W>
+__device__ __forceinline__ W word_allreduce(W v, uint32_t vmask, uint32_t ufast, int lane) {
+  if (vmask & 1u) v = word_step<0, MN, W>(v, ufast & 1u, lane);
+  if (vmask & 2u) v = word_step<1, MN, W>(v, ufast & 2u, lane);
+  if (vmask & 4u) v = word_step<2, MN, W>(v, ufast & 4u, lane);
+  if (vmask & 8u) v = word_step<3, MN, W>(v, ufast & 8u, lane);
+  if (vmask & 16u) v = word_step<4, MN, W>(v, ufast & 16u, lane);
+  if (vmask & 32u) v = word_step<5, MN, W>(v, ufast & 32u, lane);
+  return v;
+}
+
+// Signed 64-bit min / max over a lane group in two 32-bit passes: the extreme high
+// word, then the extreme low word (unsigned) among the lanes that hold it -- the
+// same order as a 64-bit comparison, and each pass a single 32-bit op per step.
+template <bool MN>
+__device__ __forceinline__ long long key_minmax(long long a, uint32_t vmask, uint32_t ufast, int lane) {
+  const int hi = (int)(uint32_t)((unsigned long long)a >> 32);
+  const uint32_t lo = (uint32_t)(unsigned long long)a;
+  const int m = word_allreduce<MN, int>(hi, vmask, ufast, lane);
+  const uint32_t cand = hi == m ? lo : (MN ? 0xFFFFFFFFu : 0u);
+  const uint32_t l = word_allreduce<MN, uint32_t>(cand, vmask, ufast, lane);
+  return (long long)(((unsigned long long)(uint32_t)m << 32) | l);
+}
+
+template <class T>
+__device__ __forceinline__ typename T::Acc lane_combine(typename T::Acc a, const DevSeg& S, int lane) {
+  const uint32_t vm = S.vmask, uf = S.ufast;
+  if constexpr (T::kFloat) {
+    if (vm & 1u) a = lane_step<0>(a, uf & 1u, lane, 0);
+    if (vm & 2u) a = lane_step<1>(a, uf & 2u, lane, 0);
+    if (vm & 4u) a = lane_step<2>(a, uf & 4u, lane, 0);
+    if (vm & 8u) a = lane_step<3>(a, uf & 8u, lane, 0);
+    if (vm & 16u) a = lane_step<4>(a, uf & 16u, lane, 0);
+    if (vm & 32u) a = lane_step<5>(a, uf & 32u, lane, 0);
+    return a;
+  } else if constexpr (T::kKey) {
+    const int op = S.op;
+    if (op == HP_OP_SUM) {
+      if (vm & 1u) a = key_sum_step<0>(a, uf & 1u, lane);
+      if (vm & 2u) a = key_sum_step<1>(a, uf & 2u, lane);
+      if (vm & 4u) a = key_sum_step<2>(a, uf & 4u, lane);
+      if (vm & 8u) a = key_sum_step<3>(a, uf & 8u, lane);
+      if (vm & 16u) a = key_sum_step<4>(a, uf & 16u, lane);
+      if (vm & 32u) a = key_sum_step<5>(a, uf & 32u, lane);
+      return a;
+    }
+    if (op == HP_OP_MIN || op == HP_OP_ARGMIN) return key_minmax<true>(a, vm, uf, lane);
+    return key_minmax<false>(a, vm, uf, lane);
+  } else {
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+      if ((vm >> b) & 1u) a = T::merge(a, T::shfl(a, 1 << b, lane), S.op);
+    return a;
+  }
+}
+
 // Combine a segment's partials across its lanes (butterfly) and waves (LDS).
 // Afterwards every lane of a group holds the group's value.
 template <class T, int KD>
 __device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const DevSeg& S, typename T::Acc a,
                                                        const Thread<KD>& th, char* lds) {
-#pragma unroll
-  for (int b = 0; b < 6; ++b)
-    if ((S.vmask >> b) & 1u) a = T::merge(a, T::shfl(a, 1 << b, th.lane), S.op);
+  if (S.vmask) a = lane_combine<T>(a, S, th.lane);
   if (S.wmask) {
     const int lanes = P.lds_slot_lanes;
     const int lidx = lanes == 1 ? 0 : (int)(th.lane & S.lds_lanes);
@@ -556,10 +749,12 @@ __device__ __forceinline__ typename T::Acc combine_seg(const DevPlan& P, const D
 }
 
 // Flat blocks (DevPlan::flat_b): add the elements of the output's block that lie
-// outside its aligned interior -- the h = (-s) mod chunk before it and the rest
-// after it -- spread over the flat_units threads that share the output (thread of
-// rank r takes elements r, r + flat_units, ...; consecutive ranks read consecutive
-// elements).  Every element of the block is inside the array, so no load leaves it.
+// outside its aligned interior -- the h = (-s) mod chunk before it and the tail
+// after it -- spread over the flat_units threads that share the output.  The tail
+// starts on a 16-byte boundary (the interior is whole vectors), so its whole vectors
+// are 16-byte loads, vector j taken by the thread of rank j mod flat_units; the h
+// head elements and the tail's last partial vector are single-element loads spread
+// the same way.  Every element of the block is inside the array, so no load leaves it.
 template <class T>
 struct RestAdd;
 template <>
@@ -576,13 +771,40 @@ template <>
 struct RestAdd<IntT> {
   __device__ static __forceinline__ void run(IAcc& a, int x, int op) { IntT::add(a, x, 0, op); }
 };
+template <>
+struct RestAdd<IntK> {
+  __device__ static __forceinline__ void run(long long& a, int x, int op) { IntK::add(a, x, 0, op); }
+};
 
-template <class T, int KD>
+// one whole vector of the tail (float sums fold it like a stream chunk; integer
+// flat blocks carry a runtime operator, so their four elements go one by one)
+template <class T, int C>
+struct RestVec {
+  using V = typename Chunk<typename T::Raw, C>::V;
+  __device__ static __forceinline__ void run(typename T::Acc& a, const typename T::Raw* p, int op) {
+    if constexpr (T::kFloat) {
+      AddChunk<T, C, HP_OP_SUM>::run(a, load_chunk<V>(p), 0, true);
+    } else if constexpr (C == 4) {
+      const V x = load_chunk<V>(p);
+      RestAdd<T>::run(a, x.x, op);
+      RestAdd<T>::run(a, x.y, op);
+      RestAdd<T>::run(a, x.z, op);
+      RestAdd<T>::run(a, x.w, op);
+    } else {
+      RestAdd<T>::run(a, load_chunk<V>(p), op);
+    }
+  }
+};
+
+template <class T, int C, int KD>
 __device__ __forceinline__ typename T::Acc flat_rest(const DevPlan& P, const typename T::Raw* __restrict__ in, long long s,
                                                   typename T::Acc a, const Thread<KD>& th) {
   const long long h = (-s) & (long long)(P.chunk - 1);
-  const long long n = P.flat_b - P.flat_e;  // h before the interior, n - h after it
-  const long long tail0 = s + P.flat_e;     // element j >= h of the rest sits at tail0 + j
+  const long long tail = s + h + P.flat_e;      // first tail element (16-byte aligned)
+  const long long tl = P.flat_b - h - P.flat_e;  // tail length
+  const long long nv = tl / C;                   // whole vectors in the tail
+  const long long ns = h + (tl - nv * C);        // single elements: the head, then the tail's end
+  const long long tv = tail + nv * C;
   long long r = 0;
 #pragma unroll
   for (int m = 0; m < KD; ++m)
@@ -591,7 +813,9 @@ __device__ __forceinline__ typename T::Acc flat_rest(const DevPlan& P, const typ
       r = r * ((long long)L.gf * L.wf * L.vf) + th.targ[m] / L.chunk;
     }
   const int op = P.seg[0].op;
-  for (long long j = r; j < n; j += P.flat_units) RestAdd<T>::run(a, in[j < h ? s + j : tail0 + j], op);
+  const long long U = P.flat_units;
+  for (long long j = r; j < nv; j += U) RestVec<T, C>::run(a, in + tail + j * C, op);
+  for (long long k = r; k < ns; k += U) RestAdd<T>::run(a, in[k < h ? s + k : tv + (k - h)], op);
   return a;
 }
 
@@ -651,7 +875,7 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
     // flat blocks have one segment walked in one outer iteration: the rest of the
     // block joins the lane partials before they are combined
     if constexpr (FL)
-      if (P.flat_b && vnone) ai = flat_rest<T, KD>(P, in, flat_s, ai, th);
+      if (P.flat_b && vnone) ai = flat_rest<T, C, KD>(P, in, flat_s, ai, th);
     ai = combine_seg<T, KD>(P, P.seg[inner], ai, th, lds);
     if (inner == stop) {
       fin = ai;
@@ -667,7 +891,7 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
             if (m >= Sp.first && m <= Sp.last && P.lv[m].ragged) vj = vj && (s[m] < th.lim[m]);
             if (m == Sp.last) t = th.targ[m] + (long long)s[m] * P.lv[m].span;
           }
-          if (vj) IntT::add(outer[j], IntT::emit(ai, P.seg[inner].op), t, Sp.op);
+          if (vj) T::add(outer[j], T::emit(ai, P.seg[inner].op), t, Sp.op);
         }
       }
       // common case: the innermost outer level has strips left, so no outer
@@ -695,7 +919,7 @@ __device__ __forceinline__ typename T::Acc reduce_block(const DevPlan& P, const 
               if (m >= Sp.first && m <= Sp.last && P.lv[m].ragged) vj = vj && (s[m] < th.lim[m]);
               if (m == Sp.last) t = th.targ[m] + (long long)s[m] * P.lv[m].span;
             }
-            if (vj) IntT::add(outer[j > 0 ? j - 1 : 0], IntT::emit(v, S.op), t, Sp.op);
+            if (vj) T::add(outer[j > 0 ? j - 1 : 0], T::emit(v, S.op), t, Sp.op);
             outer[j] = T::identity(S.op);
           } else {
             outer[j] = v;
@@ -902,12 +1126,15 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
       if (P.gmode == GCOMB_NONE) {
         if (vnone && red_writer) {
           if constexpr (T::kFloat) store_flt(P, out, o, (double)a.s + (double)a.c);
-          else store_int(P, out, o, IntT::emit(a, P.seg[0].op));
+          else store_int(P, out, o, T::emit(a, P.seg[0].op));
         }
       } else if (vnone) {  // uniform here: with a grid combine every NONE level is on G only
         // grid combine: this workgroup's partial; the fold kernel combines them
         char* part = reinterpret_cast<char*>(ws) + o * P.gsplit * kSlotBytes;
-        if (th.tid == 0) T::put(part, gred, a);
+        if (th.tid == 0) {
+          if constexpr (T::kKey) T::put_partial(part, gred, a, P.seg[P.gq].op);
+          else T::put(part, gred, a);
+        }
       }
     }
     // advance the NONE odometer

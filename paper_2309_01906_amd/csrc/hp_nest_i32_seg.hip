@@ -8,7 +8,7 @@ __global__ void __launch_bounds__(1024) k_nest_i32_seg(const DevPlan* __restrict
                                                    void* __restrict__ out, unsigned char* __restrict__ ws) {
   extern __shared__ __align__(16) char lds[];
   const DevPlan& P = *Pd;
-  wg_run<IntT, C, 3, 8, 4, false, false, true, false>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
+  wg_run<IntK, C, 3, 8, 4, false, false, true, false>(P, in, out, ws, logical_group(P, blockIdx.x), lds);
 }
 
 hp_status launch_nest_i32_seg(const DevPlan& P, const DevPlan* dP, const void* in, void* out, void* ws, size_t lds, hipStream_t st) {

@@ -645,6 +645,21 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
     dp.red_wmask |= S.wmask;
     if (S.gunits > 1) gq = j;
   }
+  // Steps whose lower lane bits are all reduced by the time they run: bits of the
+  // segment itself (steps go lowest bit first) and bits of inner segments (their
+  // combines leave every lane of a group with the group's value).
+  {
+    uint32_t inner_v = 0;
+    for (int j = dp.nseg - 1; j >= 0; --j) {
+      DevSeg& S = dp.seg[j];
+      S.ufast = 0;
+      for (int b = 0; b < 6; ++b) {
+        const uint32_t lower = (1u << b) - 1u;
+        if (((S.vmask >> b) & 1u) && ((inner_v | S.vmask) & lower) == lower) S.ufast |= 1u << b;
+      }
+      inner_v |= S.vmask;
+    }
+  }
   if (gq < 0) {
     dp.gmode = GCOMB_NONE;
     dp.gsplit = 1;
@@ -719,9 +734,38 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
       dp.kernel = HP_KERNEL_LEAN;
     else dp.kernel = d <= 4 ? HP_KERNEL_GENERIC4 : HP_KERNEL_GENERIC8;
   } else {
-    if (d <= 4 && dp.nseg <= 1) dp.kernel = HP_KERNEL_INT_FLAT;
-    else if (d <= 4 && dp.nseg <= 3) dp.kernel = HP_KERNEL_INT_SEG;
+    // The flat and segmented kernels carry one 64-bit key per lane, which packs an
+    // ARG level's (value, index) only when its child values fit in 32 bits: the
+    // input, MIN / MAX of 32-bit values, or an inner ARG level's index.  An ARG over
+    // an int64 SUM goes to the general kernel and its (value, index) pairs.
+    bool narrow = true;  // the child values of segment j fit in 32 bits
+    bool keys = true;
+    for (int j = dp.nseg - 1; j >= 0; --j) {
+      const int op = dp.seg[j].op;
+      const bool arg = op == HP_OP_ARGMIN || op == HP_OP_ARGMAX;
+      if (arg && !narrow) keys = false;
+      narrow = arg || ((op == HP_OP_MIN || op == HP_OP_MAX) && narrow);
+    }
+    if (keys && d <= 4 && dp.nseg <= 1) dp.kernel = HP_KERNEL_INT_FLAT;
+    else if (keys && d <= 4 && dp.nseg <= 3) dp.kernel = HP_KERNEL_INT_SEG;
     else dp.kernel = HP_KERNEL_INT_DEEP;
+    // The chain kernel: every reducing level a segment of its own, nothing masked,
+    // the NONE levels on the grid alone, the innermost level on lanes with at most
+    // four 16-byte chunks per lane, and in three-level chains the middle level on
+    // lanes too.
+    if (dp.kernel == HP_KERNEL_INT_SEG && dp.nseg == d - p && dp.chunk == 4 && !flat_block &&
+        dp.gmode != GCOMB_NESTED) {
+      bool ok = true;
+      for (int l = 0; l < d; ++l) {
+        const DevLevel& L = dp.lv[l];
+        if (L.ragged) ok = false;
+        if (l < p && (L.wf != 1 || L.vf != 1)) ok = false;
+      }
+      const DevLevel& LL = dp.lv[d - 1];
+      if (LL.gf != 1 || LL.wf != 1 || LL.strips > 4 || LL.chunk != 4) ok = false;
+      if (dp.nseg == 3 && (dp.lv[d - 2].gf != 1 || dp.lv[d - 2].wf != 1)) ok = false;
+      if (ok) dp.kernel = HP_KERNEL_INT_CHAIN;
+    }
   }
   // ---- info
   hp_plan_info& I = out->info;

@@ -265,3 +265,18 @@ def test_static_entry_host_errors():
     assert L.hp_reduce_static(ctypes.byref(n), None, 0, 4096, 4100, None) == 1  # misaligned fp64 output
     bad = hp.make_nest((4, 0), (0, 1), hp.F32)
     assert L.hp_reduce_static(ctypes.byref(bad), None, 0, 4096, 4096, None) == 1  # extent < 1
+
+
+def test_int_kernel_choice():
+    """Integer plans: a chain of single-level segments that divides evenly goes to the
+    chain kernel; masked levels to the segmented kernel; an ARG level over int64 sums
+    (its (value, index) does not pack into one 64-bit key) to the general kernel."""
+    i = hp.inspect((64, 128, 64, 64), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32)
+    assert i["kernel"] == hp.KERNEL_INT_CHAIN and i["kernel_name"] == "hp::k_nest_i32_chain<4, 3>"
+    i = hp.inspect((64, 128, 64), ("NONE", "MAX", "ARGMAX"), hp.I32)
+    assert i["kernel"] == hp.KERNEL_INT_CHAIN and i["kernel_name"] == "hp::k_nest_i32_chain<5, 2>"
+    assert hp.inspect((64, 100, 64, 64), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32)["kernel"] == hp.KERNEL_INT_SEG
+    assert hp.inspect((64, 128, 60, 64), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32)["kernel"] == hp.KERNEL_INT_SEG
+    assert hp.inspect((64, 128, 64), ("NONE", "ARGMIN", "SUM"), hp.I32)["kernel"] == hp.KERNEL_INT_DEEP
+    assert hp.inspect((64, 128, 64), ("NONE", "ARGMIN", "MAX"), hp.I32)["kernel"] == hp.KERNEL_INT_CHAIN
+    assert hp.inspect((64, 128, 64, 64), ("NONE", "SUM", "SUM", "MAX"), hp.I32)["kernel"] == hp.KERNEL_INT_SEG
