@@ -357,3 +357,39 @@ def test_flat_blocks(ext, op, kind):
     # a block shorter than 2c - 1 elements may hold no aligned vector: plain path
     assert info["flat_block"] == (b if b >= 2 * c - 1 else 0), info
     assert_match(got, x, ext, ops, what=f"flat {ext} {op} {kind}")
+
+
+CHAIN_CASES = [
+    # (extents, ops): chains of single-level segments that divide evenly
+    ((64, 128, 64, 64), ("NONE", "SUM", "MAX", "ARGMIN")),
+    ((16, 32, 64, 64), ("NONE", "MIN", "ARGMAX", "MAX")),
+    ((8, 16, 32, 128), ("NONE", "MAX", "SUM", "MIN")),
+    ((32, 64, 256), ("NONE", "SUM", "ARGMIN")),
+    ((32, 64, 256), ("NONE", "ARGMAX", "MIN")),
+    ((128, 32, 64), ("NONE", "MIN", "SUM")),
+    ((4, 64, 64, 64), ("NONE", "ARGMIN", "ARGMAX", "ARGMIN")),
+    ((16, 64, 64), ("SUM", "MAX", "ARGMAX")),
+]
+
+
+@pytest.mark.parametrize("ext,ops", CHAIN_CASES)
+@pytest.mark.parametrize("values", ["wide", "ties", "extreme"])
+def test_chain_kernel(ext, ops, values):
+    """The chain kernel (one operator per reducing level, every level divided evenly):
+    every innermost operator, 2- and 3-level chains, random values over the full int32
+    range, tie-heavy values in [0, 4) and rows of the extreme value a masked lane would
+    fold in; bit-exact against the oracle."""
+    import paper_2309_01906_amd as hp
+    inf = hp.inspect(ext, [hp.OP_NAMES[o] for o in ops], hp.I32)
+    assert inf["kernel"] == hp.KERNEL_INT_CHAIN, inf["kernel_name"]
+    if values == "wide":
+        x = workloads.uniform_i32(91, ext, -(2**31), 2**31 - 1)
+    elif values == "ties":
+        x = workloads.uniform_i32(92, ext, 0, 3)
+    else:
+        x = workloads.uniform_i32(93, ext, -3, 3)
+        rows = x.reshape(-1, ext[-1])
+        rows[::3] = np.iinfo(np.int32).max if ops[-1] in ("MIN", "ARGMIN") else np.iinfo(np.int32).min
+    say("case chain", ext, ops, values, inf["kernel_name"], "gsplit", inf["gsplit"])
+    got, _ = gpu_reduce(x, ext, ops)
+    assert_match(got, x, ext, ops, what=f"chain {ext} {ops} {values}")
