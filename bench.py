@@ -258,6 +258,80 @@ def extra_int_workloads(steps, warmup, stream):
     return res
 
 
+def _time_cold(plan, d, out, stream, reps, flush):
+    """p50 of `reps` runs, each after a 512 MiB read that evicts L2 and the MALL."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        flush.sum()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        plan.run(d, out, stream=stream)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ts.append(s.elapsed_time(e))
+    return pct(ts, 50)
+
+
+def extra_ragged_and_xcd(steps, warmup, stream):
+    """A 3-level-sized fp32 nest whose rows are not vector multiples, (4096, 65537)
+    (flat blocks: 16-byte loads on each row's aligned interior), beside the headline;
+    and the XCD scope: the 4-level int32 nest and a one-output 1 GiB fp32 sum
+    (viewed as (1, 8, 2^25)) with the default numbering, with XCD numbering off
+    (HP_FLAG_NO_XCD) and with an explicit X level."""
+    import torch
+
+    import oracle
+    import paper_2309_01906_amd as hp
+    import workloads
+    res = {}
+    flush = torch.zeros(128 << 20, dtype=torch.float32, device="cuda")
+    ext = (4096, 65537)
+    x = workloads.normal_f32(workloads.BASE_SEED + 6, ext)
+    d = torch.from_numpy(x).cuda()
+    with hp.Plan(ext, (hp.NONE, hp.SUM), hp.F32) as p:
+        out = p.empty_out(d.device)
+        wall, ev = time_plan(p, d, out, steps, warmup, stream)
+        nb = x.nbytes + p.info["out_bytes"]
+        got = out.cpu().numpy()
+        ref = oracle.reduce(x, ext, (0, 1), oracle.F32, threads=16)
+        sa = oracle.abs_sum(x, ext, (0, 1), oracle.F32, threads=16)
+        ok, plain, scaled = oracle.within_tolerance(got, ref, sa, 1e-6)
+        res["ragged_fp32_4096x65537"] = {
+            "bytes": nb, "kernel": p.info["kernel_name"], "flat_block": p.info["flat_block"],
+            "p50_us": round(pct(ev, 50) * 1e3, 1), "GBps": round(nb / (pct(ev, 50) * 1e-3) / 1e9, 1),
+            "all_outputs_within_1e-6": bool(ok), "max_rel_err": plain}
+    del d, x
+    xcd = {}
+    c3 = workloads.C3
+    xi = workloads.c3_input()
+    d = torch.from_numpy(xi).cuda()
+    for label, m, fl in (("default", None, 0), ("no_xcd_numbering", None, hp.FLAG_NO_XCD),
+                         ("x_on_outputs", ["X", ("GW", {"G": 16, "W": 8}), ("V", {"V": 16}), ("V", {"V": 4})], 0)):
+        with hp.Plan(c3.extents, c3.ops, c3.dtype, m, fl) as p:
+            out = p.empty_out(d.device)
+            for _ in range(warmup):
+                p.run(d, out, stream=stream)
+            xcd[f"c3_{label}_cold_us"] = round(_time_cold(p, d, out, stream, min(steps, 30), flush) * 1e3, 2)
+    del d
+    big = torch.randn(1 << 28, dtype=torch.float32, device="cuda")
+    # one sum of 2^28 floats: (1, 2^28) with the automatic map, with and without the
+    # XCD numbering; and viewed as (8, 2^25) with its first level on X
+    for label, ext, ops, m, fl in (("default", (1, 1 << 28), (hp.NONE, hp.SUM), None, 0),
+                                   ("no_xcd_numbering", (1, 1 << 28), (hp.NONE, hp.SUM), None, hp.FLAG_NO_XCD),
+                                   ("x_level", (8, 1 << 25), (hp.SUM, hp.SUM),
+                                    ["X", ("GWV", {"G": 256, "W": 8})], 0)):
+        with hp.Plan(ext, ops, hp.F32, m, fl) as p:
+            out = p.empty_out(big.device)
+            for _ in range(warmup):
+                p.run(big, out, stream=stream)
+            xcd[f"sum_1GiB_{label}_cold_us"] = round(_time_cold(p, big, out, stream, min(steps, 30), flush) * 1e3, 2)
+            xcd[f"sum_1GiB_{label}_map"] = p.info["map"]
+    del big, flush
+    res["xcd_scope"] = xcd
+    return res
+
+
 def ordered_products(stream, steps=20, warmup=3):
     """Ordered (non-commutative) products, 1 GiB each: 4096 recurrences of 16,384
     affine steps, and 4096 products of 8,192 2x2 matrices, modulo 2^64.  The values
@@ -427,8 +501,7 @@ def serve_stream(pools, duration_s, rate, warmup_s, verify):
     outs = [out.data_ptr() + 8 * int(o) for o in offs[:-1]]
     nests = [(r.nest.extents, r.nest.ops, r.nest.dtype) for r in reqs]
     with hp.Server(hbm_budget=64 << 30, slot_bytes=256 << 20, streams=4, max_batch=512, window_us=30) as srv:
-        t0 = srv.now_us() + 5000.0
-        tk = srv.replay(nests, ins, outs, [t0 + r.t_arrival_us for r in reqs])
+        tk, t0 = srv.replay_from_now(nests, ins, outs, [r.t_arrival_us for r in reqs])
         infos = [srv.wait(t) for t in tk]
         stats = srv.stats()
     arr = np.array([i["t_arrival_us"] - t0 for i in infos])
@@ -602,6 +675,8 @@ def main():
         progress("oracle timed and outputs checked")
     if not args.no_extras:
         line["extras"] = extra_int_workloads(min(args.steps, 200), min(args.warmup, 20), stream)
+        line["extras"].update(extra_ragged_and_xcd(min(args.steps, 50), min(args.warmup, 5), stream))
+        progress("ragged and XCD extras done")
         progress("2- and 4-level integer nests done")
         tc = os.path.join(ROOT, "paper_2309_01906_amd", "tune_gfx950.txt")
         if os.path.exists(tc):

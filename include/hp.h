@@ -81,8 +81,10 @@ typedef enum hp_op {
  * collapse, section 3.1); L adds nothing but allows serial strips.
  * HP_SCOPE_X names the chip's 8 XCDs, a hardware level between the grid and the
  * workgroup (section 3.2's levels by property: an XCD shares one L2).  A level on
- * X gets 8 grid units, one per XCD: its unit index is the XCD the workgroup runs
- * on.  It counts as G for every other rule (X together with W is X+W), only the
+ * X gets 8 grid units, one per XCD: all workgroups of one unit run on one XCD, as
+ * the dispatcher deals workgroups round-robin to the XCDs (which XCD holds unit 0
+ * changes from launch to launch; hp_xcd_ids checks the partition on the device).
+ * It counts as G for every other rule (X together with W is X+W), only the
  * first level that uses the grid may use it, at most one level does, and the plan
  * needs a grid of at least 16 workgroups that is a multiple of 8 with XCD
  * numbering on (no HP_FLAG_NO_XCD): else HP_EINVAL / HP_EUNSUPPORTED. */
@@ -412,6 +414,17 @@ hp_status hp_stencil_destroy(hp_stencil_t s);
  * ceiling the reduction kernels are compared with.  d_in and bytes must be
  * multiples of 16; asynchronous on `stream`. */
 hp_status hp_stream_read(const void* d_in, size_t bytes, float* d_out, int32_t grid, void* stream);
+
+/* Diagnostic of the XCD scope: launches `grid` workgroups of `threads` threads
+ * (a multiple of 64, at most 1024) with `lds_bytes` of dynamic LDS (at most
+ * 64 KiB), and thread 0 of workgroup b writes to d_out[b] the XCD it runs on, as
+ * the hardware reports it (register XCC_ID).  The XCD-aware numbering assumes the
+ * dispatcher deals workgroups round-robin to the XCDs, so that workgroups b and b'
+ * share an XCD exactly when b = b' mod 8 (which XCD takes workgroup 0 depends on
+ * where the previous launch stopped); this checks it for a launch shape.
+ * d_out: device array of `grid` int32.  Errors: HP_EINVAL for bad arguments,
+ * HP_EDEVICE for a launch failure. */
+hp_status hp_xcd_ids(int32_t* d_out, int32_t grid, int32_t threads, size_t lds_bytes, void* stream);
 
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char* hp_last_error(void);

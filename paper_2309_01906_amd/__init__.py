@@ -88,6 +88,8 @@ def lib():
         L.hp_stream_read.restype = st
         L.hp_reduce_static.argtypes = [ctypes.POINTER(Nest), ctypes.POINTER(LevelMap), ctypes.c_uint32, vp, vp, vp]
         L.hp_reduce_static.restype = st
+        L.hp_xcd_ids.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t, vp]
+        L.hp_xcd_ids.restype = st
         _lib = L
     return _lib
 
@@ -319,6 +321,16 @@ def stream_read(inp, scratch, grid: int, stream=None):
         raise ValueError("scratch needs one float per workgroup")
     check(lib().hp_stream_read(ctypes.c_void_p(inp.data_ptr()), inp.numel() * inp.element_size(),
                                ctypes.c_void_p(scratch.data_ptr()), int(grid), _stream_handle(stream)))
+
+
+def xcd_ids(grid: int, threads: int = 256, lds_bytes: int = 0, stream=None):
+    """hp_xcd_ids: the XCD that each of `grid` workgroups of `threads` threads runs on,
+    as the hardware reports it (int32 device tensor of `grid` entries)."""
+    torch = _torch()
+    out = torch.full((int(grid),), -1, dtype=torch.int32, device="cuda")
+    check(lib().hp_xcd_ids(ctypes.c_void_p(out.data_ptr()), int(grid), int(threads), int(lds_bytes),
+                           _stream_handle(stream)))
+    return out
 
 
 def reduce(inp, extents, ops, level_map=None, flags: int = 0, stream=None):
@@ -580,16 +592,33 @@ class Server:
         return {k: getattr(s, k) for k, _ in ServerStats._fields_}
 
     def replay(self, nests, in_ptrs, out_ptrs, t_arrival_us):
+        """Submit request i at server time t_arrival_us[i] (hp_server_replay)."""
+        return self._replay(nests, in_ptrs, out_ptrs, lambda: t_arrival_us)[0]
+
+    def replay_from_now(self, nests, in_ptrs, out_ptrs, offsets_us, lead_us: float = 5000.0):
+        """Submit request i at t0 + offsets_us[i], with t0 = now + lead_us read after the
+        arguments have been marshalled (for long streams that takes a noticeable time,
+        which would otherwise delay the first arrivals).  Returns (tickets, t0)."""
+        t0 = []
+
+        def times():
+            t0.append(self.now_us() + lead_us)
+            return [t0[0] + o for o in offsets_us]
+        tk = self._replay(nests, in_ptrs, out_ptrs, times)
+        return tk[0], t0[0]
+
+    def _replay(self, nests, in_ptrs, out_ptrs, times):
         n = len(nests)
         arr = (Nest * n)()
         for i, (ext, ops, dt) in enumerate(nests):
             arr[i] = make_nest(ext, ops, dt)
         ins = (ctypes.c_void_p * n)(*in_ptrs)
         outs = (ctypes.c_void_p * n)(*out_ptrs)
-        ts = (ctypes.c_double * n)(*t_arrival_us)
         tk = (ctypes.c_uint64 * n)()
+        ts = (ctypes.c_double * n)()
+        ts[:] = times()
         check(lib().hp_server_replay(self._h, n, arr, ins, outs, ts, tk))
-        return list(tk)
+        return list(tk), None
 
     def close(self):
         if self._h:

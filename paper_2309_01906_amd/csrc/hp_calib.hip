@@ -44,3 +44,25 @@ extern "C" hp_status hp_stream_read(const void* d_in, size_t bytes, float* d_out
   if (hipGetLastError() != hipSuccess) return hp::fail(HP_EDEVICE, "launch failed");
   return HP_OK;
 }
+
+namespace {
+
+// The XCD (accelerator complex die) each workgroup runs on, read from the
+// hardware register XCC_ID (bits 3:0): thread 0 of workgroup b writes it to out[b].
+__global__ void __launch_bounds__(1024) k_xcd_ids(int32_t* __restrict__ out) {
+  const uint32_t id = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);  // hwreg(HW_REG_XCC_ID, 0, 4)
+  if (threadIdx.x == 0) out[blockIdx.x] = (int32_t)(id & 0xFu);
+}
+
+}  // namespace
+
+extern "C" hp_status hp_xcd_ids(int32_t* d_out, int32_t grid, int32_t threads, size_t lds_bytes, void* stream) {
+  if (!d_out) return hp::fail(HP_EINVAL, "null output");
+  if (grid < 1 || grid > (1 << 20)) return hp::fail(HP_EINVAL, "grid %d outside [1, 2^20]", grid);
+  if (threads < 64 || threads > 1024 || threads % 64) return hp::fail(HP_EINVAL, "threads %d not 64..1024 in 64s", threads);
+  if (lds_bytes > 65536) return hp::fail(HP_EINVAL, "lds_bytes %zu above 64 KiB", lds_bytes);
+  hipLaunchKernelGGL(k_xcd_ids, dim3((unsigned)grid), dim3((unsigned)threads), lds_bytes,
+                     reinterpret_cast<hipStream_t>(stream), d_out);
+  if (hipGetLastError() != hipSuccess) return hp::fail(HP_EDEVICE, "launch failed");
+  return HP_OK;
+}

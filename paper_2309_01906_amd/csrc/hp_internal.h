@@ -31,6 +31,16 @@ enum GMode : int32_t {
   GCOMB_NESTED = 2    // several segments span workgroups (outer ones have one strip)
 };
 
+// Division by a plan constant d of a dividend 0 <= n < 2^31 as one 64-bit product
+// and a shift: q = (n * m) >> s with s = 31 + ceil(log2 d), m = ceil(2^s / d)
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994: m d = 2^s + e with 0 <= e < d <= 2^(s - 31), so the
+// error term n e / (d 2^s) stays below 1/d and never reaches the next integer).
+// m = 0 marks a divisor whose dividends may not fit 31 bits: plain division.
+struct FastDiv {
+  uint32_t m, s;
+};
+
 struct DevLevel {
   int64_t e;        // extent
   int64_t stride;   // elements between consecutive iterations
@@ -46,6 +56,11 @@ struct DevLevel {
   int32_t chunk;    // consecutive iterations per unit per strip
   int32_t seg;      // segment index, -1 for NONE levels
   int32_t ragged;   // some unit may see t >= e on some strip
+  FastDiv fd_gdiv;  // divisions by gdiv and gf (workgroup digits, always < 2^31)
+  FastDiv fd_gf;
+  FastDiv fd_span;  // division by span for the strips in bounds (m = 0 when e + span >= 2^31)
+  int32_t csh;      // log2(chunk)
+  int32_t pad_;
 };
 
 struct DevSeg {

@@ -82,6 +82,16 @@ __device__ __forceinline__ void two_sum(F a, F b, F& s, F& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
+// n / d by the plan's FastDiv of d (plain division when it has none)
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f, uint32_t d) {
+  return f.m ? (uint32_t)(((unsigned long long)n * f.m) >> f.s) : n / d;
+}
+// the digit of a level in the workgroup's G coordinate: (g / gdiv) % gf
+__device__ __forceinline__ uint32_t g_digit(uint32_t g, const DevLevel& L) {
+  const uint32_t q = fdiv(g, L.fd_gdiv, L.gdiv);
+  return q - fdiv(q, L.fd_gf, L.gf) * L.gf;
+}
+
 // ---------------------------------------------------------------------------
 // carriers
 
@@ -810,7 +820,7 @@ __device__ __forceinline__ typename T::Acc flat_rest(const DevPlan& P, const typ
   for (int m = 0; m < KD; ++m)
     if (m >= P.p && m < P.depth) {
       const DevLevel& L = P.lv[m];
-      r = r * ((long long)L.gf * L.wf * L.vf) + th.targ[m] / L.chunk;
+      r = r * ((long long)L.gf * L.wf * L.vf) + (th.targ[m] >> L.csh);
     }
   const int op = P.seg[0].op;
   const long long U = P.flat_units;
@@ -1069,13 +1079,16 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
     th.targ[m] = 0;
     if (m < P.depth) {
       const DevLevel& L = P.lv[m];
-      const uint32_t ug = (g / L.gdiv) % L.gf;
+      const uint32_t ug = g_digit(g, L);
       const uint32_t uw = ((uint32_t)th.w >> L.wsh) & (uint32_t)(L.wf - 1);
       const uint32_t uv = ((uint32_t)th.lane >> L.vsh) & (uint32_t)(L.vf - 1);
       const long long t0 = (long long)(((unsigned long long)ug * L.wf + uw) * L.vf + uv) * L.chunk;
       // a level without a ragged tail has every strip in range (t0 < span), and
       // lim is only read for ragged levels: skip the per-lane division there
-      th.lim[m] = !L.ragged ? (int)L.strips : t0 < L.e ? (int)((L.e - t0 + L.span - 1) / L.span) : 0;
+      if (!L.ragged) th.lim[m] = (int)L.strips;
+      else if (t0 >= L.e) th.lim[m] = 0;
+      else if (L.fd_span.m) th.lim[m] = (int)fdiv((uint32_t)(L.e - t0 + L.span - 1), L.fd_span, (uint32_t)L.span);
+      else th.lim[m] = (int)((L.e - t0 + L.span - 1) / L.span);
       th.targ[m] = (int)t0;
       if (m < P.p) {
         base_none += t0 * L.stride;
@@ -1157,6 +1170,11 @@ __device__ __forceinline__ void wg_run(const DevPlan& P, const typename T::Raw* 
   }
 }
 
+// XCD-aware numbering: the dispatcher deals workgroups round-robin to the 8 XCDs
+// (measured with hp_xcd_ids: workgroup b runs on XCD (b + c) mod 8, c fixed within a
+// launch), so physical workgroups with one residue b mod 8 share an XCD and its L2.
+// They get one contiguous range of logical workgroups -- the outermost grid digit,
+// which an X level of the map takes.
 __device__ __forceinline__ uint32_t logical_group(const DevPlan& P, uint32_t b) {
   if (!P.xcd) return b;
   const uint32_t per = (uint32_t)P.grid >> 3;  // grid % 8 == 0 when xcd is set

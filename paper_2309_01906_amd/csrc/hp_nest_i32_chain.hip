@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(1024) k_nest_i32_chain(const DevPlan* __restri
   for (int m = 0; m < 4; ++m) {
     if (m < d) {
       const DevLevel& L = P.lv[m];
-      const uint32_t ug = (g / L.gdiv) % L.gf;
+      const uint32_t ug = g_digit(g, L);
       const uint32_t uw = ((uint32_t)th.w >> L.wsh) & (uint32_t)(L.wf - 1);
       const uint32_t uv = ((uint32_t)th.lane >> L.vsh) & (uint32_t)(L.vf - 1);
       const long long t0 = (long long)(((unsigned long long)ug * L.wf + uw) * L.vf + uv) * L.chunk;

@@ -48,6 +48,14 @@ static inline int nest_high(uint32_t s) { return s == HP_SCOPE_L ? highbit(s) : 
 
 static int elem_bytes(int dt) { return dt == HP_BF16 ? 2 : 4; }
 
+// Magic numbers of FastDiv for a divisor 1 <= d < 2^31.
+static FastDiv fastdiv(uint64_t d) {
+  const int l = log2u(d);  // ceil(log2 d)
+  const uint32_t s = 31u + (uint32_t)l;
+  const uint64_t m = ((uint64_t)1 << s) / d + (((uint64_t)1 << s) % d != 0);
+  return FastDiv{(uint32_t)m, s};
+}
+
 // Automatic map: NONE levels on the grid; reducing levels fill the lanes of a
 // wavefront from the innermost level outward (shuffles are the cheapest combine),
 // then the waves of a workgroup (LDS + barrier), then, when the outputs alone do
@@ -617,6 +625,15 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
       os *= dp.lv[l].e;
     }
     dp.n_out = os;
+  }
+  // ---- divisions the kernels make by plan constants
+  for (int l = 0; l < d; ++l) {
+    DevLevel& L = dp.lv[l];
+    L.fd_gdiv = fastdiv((uint64_t)L.gdiv);
+    L.fd_gf = fastdiv((uint64_t)L.gf);
+    L.fd_span = (L.e + L.span < ((int64_t)1 << 31)) ? fastdiv((uint64_t)L.span) : FastDiv{0u, 0u};
+    L.csh = log2u((uint64_t)L.chunk);
+    L.pad_ = 0;
   }
   // ---- segment masks and the grid-combine mode
   dp.red_vmask = dp.red_wmask = 0;

@@ -52,11 +52,12 @@ def main():
         keys = keys[: args.limit]
     hp.tune_cache_clear()
     t0 = time.perf_counter()
-    for k in keys:
+    for i, k in enumerate(keys):
         n = reps[k]
         best, auto = hp.tune(n.extents, n.ops, n.dtype, reps=args.reps)
-        print(f"class {k}: shape {n.extents} auto {auto:.1f} us -> tuned {best:.1f} us", flush=True)
-    hp.tune_cache_save(args.out)
+        print(f"class {i + 1}/{len(keys)} {k}: shape {n.extents} auto {auto:.1f} us -> tuned {best:.1f} us "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        hp.tune_cache_save(args.out)  # after every class, so an interrupted run keeps what it has
     print(f"{len(keys)} classes tuned in {time.perf_counter() - t0:.1f} s -> {args.out}", flush=True)
 
 

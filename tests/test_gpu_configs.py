@@ -113,9 +113,8 @@ def test_c5_full_size_stream_served():
         outs.append(torch.full((inf["n_out"],), -7, dtype=hp.torch_out_dtype(inf["out_dtype"]), device="cuda"))
     ins = [(di if r.pool == 0 else df).data_ptr() + 4 * r.offset for r in reqs]
     with hp.Server(hbm_budget=64 << 30, slot_bytes=256 << 20, streams=4, max_batch=512, window_us=30) as s:
-        t0 = s.now_us() + 5000.0
-        tk = s.replay([(r.nest.extents, r.nest.ops, r.nest.dtype) for r in reqs], ins, [o.data_ptr() for o in outs],
-                      [t0 + r.t_arrival_us for r in reqs])
+        tk, t0 = s.replay_from_now([(r.nest.extents, r.nest.ops, r.nest.dtype) for r in reqs], ins,
+                                   [o.data_ptr() for o in outs], [r.t_arrival_us for r in reqs])
         infos = [s.wait(t) for t in tk]
         stats = s.stats()
     assert all(i["status"] == 0 for i in infos) and stats["failed"] == 0

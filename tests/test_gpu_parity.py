@@ -267,6 +267,34 @@ def test_xcd_scope_maps():
     assert n == 3
 
 
+def test_xcd_ids_follow_the_x_digit():
+    """The XCD-aware numbering assumes the dispatcher deals workgroups round-robin to
+    the 8 XCDs, so that workgroups b and b' share an XCD (and its L2) exactly when
+    b = b' mod 8: the X digit of a plan then names one XCD's workgroups.  (Which XCD
+    takes workgroup 0 depends on where the previous launch stopped, so the test
+    checks the partition, not the index.)  The hardware's XCC_ID register of every
+    workgroup, for the launch shapes of X-mapped plans, of the benchmarked nests and
+    of large grids, must be (b + c) mod 8 for one c per launch."""
+    import paper_2309_01906_amd as hp
+    shapes = []
+    for ext, ops, m in [(workloads.C3.extents, workloads.C3.ops,
+                         ["X", ("GW", {"G": 16, "W": 8}), ("V", {"V": 16}), ("V", {"V": 4})]),
+                        ((64, 64, 256), (1, 1, 1), ["X", ("GW", {"G": 4, "W": 4}), "V"]),
+                        ((3, 1000, 100), (0, 1, 1), ["X", ("GW", {"G": 2, "W": 2}), "V"])]:
+        inf = hp.inspect(ext, ops, hp.I32 if ext == workloads.C3.extents else hp.F32, m)
+        shapes.append((inf["grid"], 64 * inf["waves"], inf["lds_bytes"]))
+    for nest in (workloads.C2, workloads.C3):
+        inf = hp.inspect(nest.extents, nest.ops, nest.dtype)
+        shapes.append((inf["grid"], 64 * inf["waves"], inf["lds_bytes"]))
+    shapes += [(8, 64, 0), (4096, 1024, 0), (65536, 256, 0)]
+    for grid, threads, lds in shapes:
+        ids = hp.xcd_ids(grid, threads, lds).cpu().numpy()
+        torch.cuda.synchronize()
+        want = (np.arange(grid) + ids[0]) % 8
+        say("case xcd ids", grid, threads, lds, "workgroup 0 on XCD", int(ids[0]))
+        np.testing.assert_array_equal(ids, want, err_msg=f"grid {grid} threads {threads}")
+
+
 def test_flags_scalar_out_f32_noxcd_generic():
     import paper_2309_01906_amd as hp
     x = workloads.normal_f32(73, (256, 4096))

@@ -98,6 +98,20 @@ def test_replay_open_loop_timestamps():
     assert all(i["t_admit_us"] >= i["t_arrival_us"] for i in infos)
 
 
+def test_replay_from_now_fixes_the_start_after_marshalling():
+    """replay_from_now reads the start time only once the stream's arguments are
+    marshalled, so a long stream's first requests are not submitted after their
+    arrival times; arrivals are the start plus the offsets."""
+    with fake(streams=2) as s:
+        offsets = [25.0 * i for i in range(2000)]
+        before = s.now_us()
+        tk, t0 = s.replay_from_now([NEST] * 2000, [0] * 2000, [0] * 2000, offsets, lead_us=2000.0)
+        infos = [s.wait(t) for t in tk]
+    assert t0 >= before + 2000.0
+    assert [i["t_arrival_us"] for i in infos] == [t0 + o for o in offsets]
+    assert all(i["t_admit_us"] >= i["t_arrival_us"] for i in infos)
+
+
 def test_invalid_config_and_nest():
     with pytest.raises(hp.HPError):
         hp.Server(streams=0, flags=hp.SERVER_FAKE_DEVICE)
