@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "achieved HBM GB/s (% of peak) for nested reduction; batched-vs-plain; p50/p99"
 PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-KERNEL_SOURCES = ["hp_nest.h", "hp_nest_f32.hip", "hp_internal.h", "hp_plan.cpp"]
+KERNEL_SOURCES = ["hp_nest.h", "hp_lanes.h", "hp_nest_f32.hip", "hp_internal.h", "hp_plan.cpp"]
 
 
 def kernel_hash() -> str:

@@ -120,6 +120,33 @@ hp_status warm_batch_kernels(hipStream_t st) {
   return HP_OK;
 }
 
+// The SimpleDesc of a plan, if it has that form (see hp_batch_dev.h).
+bool simple_desc_of(const DevPlan& P, SimpleDesc* D) {
+  if (P.dtype != HP_F32 && P.dtype != HP_BF16) return false;
+  const int c = P.dtype == HP_BF16 ? 8 : 4;
+  if (P.depth != 2 || P.p != 1 || P.nseg != 1 || P.seg[0].op != HP_OP_SUM || P.gmode != GCOMB_NONE) return false;
+  const DevLevel& L0 = P.lv[0];
+  const DevLevel& L1 = P.lv[1];
+  if (L1.gf != 1 || L1.wf != 1 || L1.vsh != 0 || L1.chunk != c || L1.ragged || L1.stride != 1) return false;
+  if (L0.wf != 1 || L0.chunk != 1 || L0.ostride != 1 || (L0.vf > 1 && (1 << L0.vsh) != L1.vf)) return false;
+  if (L0.e > 0x7fffffffLL || L0.strips > 0x7fffffffLL || L1.strips > 0x7fffffffLL) return false;
+  if (L0.gdiv != 1 || (int64_t)L0.gf != P.grid) return false;
+  memset(D, 0, sizeof *D);
+  D->block = L0.stride;
+  D->flat_b = P.flat_b;
+  D->flat_e = P.flat_e;
+  D->e0 = (int32_t)L0.e;
+  D->g0 = (int32_t)L0.gf;
+  D->v0sh = L0.vf > 1 ? L0.vsh : 0;
+  D->v0 = L0.vf;
+  D->v1 = L1.vf;
+  D->strips1 = (int32_t)L1.strips;
+  D->strips0 = (int32_t)L0.strips;
+  D->ufast = P.seg[0].ufast;
+  D->out_f64 = P.out_kind == OUT_F64 ? 1 : 0;
+  return true;
+}
+
 void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B) {
   const int nq = grid < kQueues ? (grid < 1 ? 1 : grid) : kQueues;
   int pos = 0;
@@ -284,6 +311,17 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
       return fail(HP_ETOOBIG, "batch group has %lld tasks, more than 2^31 - 1", ntask[g]);
     }
   }
+  // compact descriptors of the nests whose plans have the simple form (float
+  // families of depth <= 4 only: those kernels hold the simple path)
+  const size_t simple_off = arena_bytes;
+  arena_bytes = align_up(arena_bytes + (size_t)n * sizeof(SimpleDesc), 256);
+  std::vector<SimpleDesc> simple((size_t)n);
+  std::vector<char> is_simple((size_t)n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const DevPlan& P = b->plans[(size_t)i];
+    const int fam = family_of(P);
+    if ((fam == FAM_F32_4 || fam == FAM_BF16_4) && simple_desc_of(P, &simple[(size_t)i])) is_simple[(size_t)i] = 1;
+  }
   std::vector<hp::FoldTask> folds;
   b->fold_beg.assign((size_t)n + 1, 0);
   for (int64_t i = 0; i < n; ++i) {
@@ -311,6 +349,7 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
   b->d_out = reinterpret_cast<void**>(const_cast<void**>(b->d_in + n));
   b->d_ws = reinterpret_cast<unsigned char**>(const_cast<void**>(b->d_in + 2 * n));
   std::vector<unsigned char> host_arena(arena_bytes, 0);
+  memcpy(host_arena.data() + simple_off, simple.data(), (size_t)n * sizeof(SimpleDesc));
   if (!folds.empty()) memcpy(host_arena.data() + fold_off, folds.data(), folds.size() * sizeof(hp::FoldTask));
   b->d_fold = reinterpret_cast<hp::FoldTask*>((unsigned char*)b->arena + fold_off);
   b->ws_ptrs.assign((size_t)n, nullptr);
@@ -327,7 +366,8 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
     std::vector<int2> ordered((size_t)ntask[g]);
     long long k = 0;
     for (int64_t i : mem)
-      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w) ordered[(size_t)k++] = make_int2((int)i, (int)w);
+      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w)
+        ordered[(size_t)k++] = make_int2((int)i, (int)w | (is_simple[(size_t)i] ? kSimpleTask : 0));
     Group G;
     G.family = keys[g].first;
     G.chunk = keys[g].second;
@@ -346,6 +386,7 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
     deal_tasks(ordered.data(), (int)ntask[g], G.grid, reinterpret_cast<int2*>(host_arena.data() + task_off[g]),
                &G.args);
     G.args.tasks = reinterpret_cast<const int2*>((unsigned char*)b->arena + task_off[g]);
+    G.args.simple = reinterpret_cast<const SimpleDesc*>((unsigned char*)b->arena + simple_off);
     G.args.ctr = reinterpret_cast<unsigned int*>((unsigned char*)b->arena + ctr_off[g]);
     b->groups.push_back(G);
   }

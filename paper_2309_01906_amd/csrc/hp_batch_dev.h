@@ -8,14 +8,39 @@ namespace hp {
 // Persistent batched kernels: workers pop (nest, workgroup) tasks with atomic
 // counters -- a dynamic schedule on the grid level.  The tasks are dealt, largest
 // first, into kQueues queues with one counter each; workgroup b takes from queue
-// b % kQueues, which is the XCD the hardware places it on, so the counters are
-// contended by one XCD each instead of the whole chip.  Every run leaves the
+// b % kQueues, which sits on one XCD (workgroups are dealt round-robin to the 8
+// XCDs).  Atomics on one address are serialised in the L2 (some 20 ns apiece), so
+// a batch of tens of thousands of small tasks needs many counters: 64 queues, 8
+// per XCD, each shared by an eighth of an XCD's workers.  Every run leaves the
 // counters at zero for the next one, so a run can be replayed from a graph: the
 // fold kernel that ends a run with grid-split nests clears them (the persistent
 // launches before it on the stream have finished), and a batch without fold tasks
 // clears them with a small kernel before each persistent launch.
-constexpr int kQueues = 8;
+constexpr int kQueues = 64;
 constexpr int kCtrStride = 64;  // counters 256 bytes apart
+
+// Compact form of the most common batched plan -- one float SUM over each output's
+// contiguous block, the block on lanes of one wave (16-byte chunks, whole strips,
+// possibly the aligned interior of a flat block), the outputs on the grid and on
+// the remaining lanes -- so a task reads one 64-byte line of descriptor instead of
+// the plan's fields.  The arithmetic, and its order, is the general path's: the
+// same chunk folds, the same flat-block rest, the same butterfly, so the bits are
+// those of the nest's own plan run alone.
+struct alignas(64) SimpleDesc {
+  int64_t block;     // elements between consecutive outputs' blocks
+  int64_t flat_b;    // 0, or the flat block length (the interior is flat_e elements)
+  int64_t flat_e;
+  int32_t e0;        // outputs
+  int32_t g0;        // grid units of the output level
+  int32_t v0sh;      // lane bit of the output level (log2 of the lanes per output)
+  int32_t v0;        // output lanes groups per wave
+  int32_t v1;        // lanes per output
+  int32_t strips1;   // interior chunks per lane
+  int32_t strips0;   // output strips
+  uint32_t ufast;    // butterfly steps that may take the uniform form
+  int32_t out_f64;   // output type: fp64 (else fp32)
+  int32_t pad;
+};
 
 struct BatchArgs {
   const DevPlan* plans;        // one plan per nest
@@ -26,7 +51,59 @@ struct BatchArgs {
   unsigned char* const* wss;   // per nest (grid-combine workspace, may be null)
   int qbeg[kQueues + 1];       // queue q holds tasks [qbeg[q], qbeg[q+1])
   int per_pop;                 // tasks taken per atomic
+  const SimpleDesc* simple;    // per nest; read for tasks marked kSimpleTask (may be null)
 };
+constexpr int kSimpleTask = (int)0x80000000;  // task's workgroup field: the nest has a SimpleDesc
+
+// One task of a SimpleDesc nest: output strip s0 of this task's outputs, each lane
+// a unit of the output level (bits >= v0sh) and of the block (bits < v0sh).
+template <class T, int C>
+__device__ __forceinline__ void simple_task(const SimpleDesc& D, const typename T::Raw* __restrict__ in,
+                                            void* __restrict__ out, uint32_t g, int lane) {
+  using V = typename Chunk<typename T::Raw, C>::V;
+  const int v1 = D.v1;
+  const int uv1 = lane & (v1 - 1);
+  const int uv0 = (lane >> D.v0sh) & (D.v0 - 1);
+  const bool real = lane < D.v0 * v1;  // lanes beyond both levels' units are idle
+  const long long span1 = (long long)v1 * C;
+  DevSeg S;
+  S.vmask = (uint32_t)(v1 - 1);
+  S.ufast = D.ufast;
+  S.op = HP_OP_SUM;
+  for (int s0 = 0; s0 < D.strips0; ++s0) {
+    const long long o = ((long long)g * D.v0 + uv0) + (long long)s0 * D.g0 * D.v0;
+    const bool valid = o < D.e0;
+    const long long sb = (valid ? o : 0) * D.block;  // an invalid lane reads output 0's block
+    const long long h = D.flat_b ? ((-sb) & (long long)(C - 1)) : 0;
+    const typename T::Raw* __restrict__ p = in + sb + h + (long long)uv1 * C;
+    FAcc a = T::identity(0);
+    // the interior: strips1 chunks, four loads in flight
+    int f = 0;
+    for (; f + 4 <= D.strips1; f += 4) {
+      V x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = load_chunk<V>(p + (long long)(f + u) * span1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) AddChunk<T, C, HP_OP_SUM>::run(a, x[u], 0, true);
+    }
+    for (; f < D.strips1; ++f) AddChunk<T, C, HP_OP_SUM>::run(a, load_chunk<V>(p + (long long)f * span1), 0, true);
+    if (D.flat_b) {  // the rest of a flat block, in flat_rest's order
+      const long long tail = sb + h + D.flat_e;
+      const long long tl = D.flat_b - h - D.flat_e;
+      const long long nv = tl / C;
+      const long long ns = h + (tl - nv * C);
+      const long long tv = tail + nv * C;
+      for (long long j = uv1; j < nv; j += v1) RestVec<T, C>::run(a, in + tail + j * C, HP_OP_SUM);
+      for (long long k = uv1; k < ns; k += v1) RestAdd<T>::run(a, in[k < h ? sb + k : tv + (k - h)], HP_OP_SUM);
+    }
+    a = lane_combine<T>(a, S, lane);
+    if (valid && real && uv1 == 0) {
+      const double v = (double)a.s + (double)a.c;
+      if (D.out_f64) reinterpret_cast<double*>(out)[o] = v;
+      else reinterpret_cast<float*>(out)[o] = (float)v;
+    }
+  }
+}
 
 // Wave tasks: every wavefront of the workgroup is an independent worker running
 // one-wave plans (no workgroup barrier), with its own small slice of LDS.  The next
@@ -68,6 +145,7 @@ __device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
   long long t0 = (long long)qb + (long long)r * k;
   int t = t0 < qe ? (int)t0 : qe;
   int t_end = t0 + k < qe ? (int)(t0 + k) : qe;
+  typedef const __attribute__((address_space(4))) SimpleDesc CSimple;
   while (t < t_end) {
     const int x = __builtin_amdgcn_readfirstlane(tasks[2 * (long long)t]);
     const int y = __builtin_amdgcn_readfirstlane(tasks[2 * (long long)t + 1]);
@@ -75,6 +153,16 @@ __device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
     if (u == t_end) {
       u = pop();
       u_end = u + k < qe ? u + k : qe;
+    }
+    if constexpr (T::kFloat && KD == 4) {
+      if (y & kSimpleTask) {
+        simple_task<T, C>(*(const SimpleDesc*)((CSimple*)B.simple + x),
+                          reinterpret_cast<const typename T::Raw*>(B.ins[x]), B.outs[x],
+                          (uint32_t)(y & ~kSimpleTask), lane);
+        t = u;
+        t_end = u_end;
+        continue;
+      }
     }
     wg_run<T, C, NS, U, KD, false, true, PF>(*(const DevPlan*)(plans + x),
                                              reinterpret_cast<const typename T::Raw*>(B.ins[x]), B.outs[x],
