@@ -129,21 +129,21 @@ bool simple_desc_of(const DevPlan& P, SimpleDesc* D) {
   const DevLevel& L1 = P.lv[1];
   if (L1.gf != 1 || L1.wf != 1 || L1.vsh != 0 || L1.chunk != c || L1.ragged || L1.stride != 1) return false;
   if (L0.wf != 1 || L0.chunk != 1 || L0.ostride != 1 || (L0.vf > 1 && (1 << L0.vsh) != L1.vf)) return false;
-  if (L0.e > 0x7fffffffLL || L0.strips > 0x7fffffffLL || L1.strips > 0x7fffffffLL) return false;
+  const int64_t lim = 0x7fffffffLL;
+  if (L0.e > lim || L0.strips > lim || L1.strips > lim || L0.stride > lim || P.flat_b > lim) return false;
   if (L0.gdiv != 1 || (int64_t)L0.gf != P.grid) return false;
   memset(D, 0, sizeof *D);
-  D->block = L0.stride;
-  D->flat_b = P.flat_b;
-  D->flat_e = P.flat_e;
+  D->block = (int32_t)L0.stride;
+  D->flat_b = (int32_t)P.flat_b;
+  D->flat_e = (int32_t)P.flat_e;
   D->e0 = (int32_t)L0.e;
   D->g0 = (int32_t)L0.gf;
-  D->v0sh = L0.vf > 1 ? L0.vsh : 0;
   D->v0 = L0.vf;
   D->v1 = L1.vf;
   D->strips1 = (int32_t)L1.strips;
   D->strips0 = (int32_t)L0.strips;
-  D->ufast = P.seg[0].ufast;
-  D->out_f64 = P.out_kind == OUT_F64 ? 1 : 0;
+  D->bits = (uint32_t)(L0.vf > 1 ? L0.vsh : 0) | (P.out_kind == OUT_F64 ? 0x100u : 0u) |
+            ((P.seg[0].ufast & 0x3Fu) << 16);
   return true;
 }
 
@@ -204,6 +204,9 @@ struct hp_batch_s {
   hp::FoldTask* d_fold = nullptr;  // in the arena
   int n_fold = 0;
   std::vector<int> fold_beg;      // nest i's fold tasks: [fold_beg[i], fold_beg[i + 1])
+  std::vector<hp::SimpleDesc> simple;  // host copy of the compact descriptors (pointers set by set_io)
+  std::vector<char> is_simple;
+  hp::SimpleDesc* d_simple = nullptr;  // in the arena
   bool io_set = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -350,6 +353,9 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
   b->d_ws = reinterpret_cast<unsigned char**>(const_cast<void**>(b->d_in + 2 * n));
   std::vector<unsigned char> host_arena(arena_bytes, 0);
   memcpy(host_arena.data() + simple_off, simple.data(), (size_t)n * sizeof(SimpleDesc));
+  b->d_simple = reinterpret_cast<SimpleDesc*>((unsigned char*)b->arena + simple_off);
+  b->simple.swap(simple);
+  b->is_simple.swap(is_simple);
   if (!folds.empty()) memcpy(host_arena.data() + fold_off, folds.data(), folds.size() * sizeof(hp::FoldTask));
   b->d_fold = reinterpret_cast<hp::FoldTask*>((unsigned char*)b->arena + fold_off);
   b->ws_ptrs.assign((size_t)n, nullptr);
@@ -367,7 +373,7 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
     long long k = 0;
     for (int64_t i : mem)
       for (long long w = 0; w < b->plans[(size_t)i].grid; ++w)
-        ordered[(size_t)k++] = make_int2((int)i, (int)w | (is_simple[(size_t)i] ? kSimpleTask : 0));
+        ordered[(size_t)k++] = make_int2((int)i, (int)w | (b->is_simple[(size_t)i] ? kSimpleTask : 0));
     Group G;
     G.family = keys[g].first;
     G.chunk = keys[g].second;
@@ -386,7 +392,7 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
     deal_tasks(ordered.data(), (int)ntask[g], G.grid, reinterpret_cast<int2*>(host_arena.data() + task_off[g]),
                &G.args);
     G.args.tasks = reinterpret_cast<const int2*>((unsigned char*)b->arena + task_off[g]);
-    G.args.simple = reinterpret_cast<const SimpleDesc*>((unsigned char*)b->arena + simple_off);
+    G.args.simple = b->d_simple;
     G.args.ctr = reinterpret_cast<unsigned int*>((unsigned char*)b->arena + ctr_off[g]);
     b->groups.push_back(G);
   }
@@ -440,8 +446,17 @@ extern "C" hp_status hp_batch_set_io(hp_batch_t b, const void* const* d_in, void
     b->exec_each = nullptr;
     b->graph_each = nullptr;
   }
+  bool any_simple = false;
+  for (int64_t i = 0; i < b->n; ++i)
+    if (b->is_simple[(size_t)i]) {
+      b->simple[(size_t)i].in = d_in[i];
+      b->simple[(size_t)i].out = d_out[i];
+      any_simple = true;
+    }
   if (hipMemcpy(b->d_in, d_in, sizeof(void*) * (size_t)b->n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_out, d_out, sizeof(void*) * (size_t)b->n, hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(b->d_out, d_out, sizeof(void*) * (size_t)b->n, hipMemcpyHostToDevice) != hipSuccess ||
+      (any_simple && hipMemcpy(b->d_simple, b->simple.data(), sizeof(hp::SimpleDesc) * (size_t)b->n,
+                               hipMemcpyHostToDevice) != hipSuccess))
     return hp::fail(HP_EDEVICE, "pointer table upload failed");
   b->io_set = true;
   return HP_OK;

@@ -22,24 +22,25 @@ constexpr int kCtrStride = 64;  // counters 256 bytes apart
 // Compact form of the most common batched plan -- one float SUM over each output's
 // contiguous block, the block on lanes of one wave (16-byte chunks, whole strips,
 // possibly the aligned interior of a flat block), the outputs on the grid and on
-// the remaining lanes -- so a task reads one 64-byte line of descriptor instead of
-// the plan's fields.  The arithmetic, and its order, is the general path's: the
-// same chunk folds, the same flat-block rest, the same butterfly, so the bits are
-// those of the nest's own plan run alone.
+// the remaining lanes -- so a task reads one 64-byte line (the nest's input and
+// output pointers included, written when the batch's pointers are set) instead of
+// the plan's fields and the pointer tables.  The arithmetic, and its order, is the
+// general path's: the same chunk folds, the same flat-block rest, the same
+// butterfly, so the bits are those of the nest's own plan run alone.
 struct alignas(64) SimpleDesc {
-  int64_t block;     // elements between consecutive outputs' blocks
-  int64_t flat_b;    // 0, or the flat block length (the interior is flat_e elements)
-  int64_t flat_e;
+  const void* in;
+  void* out;
+  int32_t block;     // elements between consecutive outputs' blocks
+  int32_t flat_b;    // 0, or the flat block length (the interior is flat_e elements)
+  int32_t flat_e;
   int32_t e0;        // outputs
   int32_t g0;        // grid units of the output level
-  int32_t v0sh;      // lane bit of the output level (log2 of the lanes per output)
-  int32_t v0;        // output lanes groups per wave
+  int32_t v0;        // output lane groups per wave
   int32_t v1;        // lanes per output
   int32_t strips1;   // interior chunks per lane
   int32_t strips0;   // output strips
-  uint32_t ufast;    // butterfly steps that may take the uniform form
-  int32_t out_f64;   // output type: fp64 (else fp32)
-  int32_t pad;
+  uint32_t bits;     // v0sh (bits 0-7: lane bit of the output level), fp64 output (bit 8),
+                     // butterfly steps that may take the uniform form (bits 16-21)
 };
 
 struct BatchArgs {
@@ -56,26 +57,54 @@ struct BatchArgs {
 constexpr int kSimpleTask = (int)0x80000000;  // task's workgroup field: the nest has a SimpleDesc
 
 // One task of a SimpleDesc nest: output strip s0 of this task's outputs, each lane
-// a unit of the output level (bits >= v0sh) and of the block (bits < v0sh).
+// a unit of the output level (bits >= v0sh) and of the block (bits < v0sh).  The
+// first elements of a flat block's rest are loaded before the interior, so their
+// round trip to memory overlaps the stream; they are added after it, as the
+// general path adds them.
+constexpr int kRestVecPre = 2, kRestOnePre = 2;
+
 template <class T, int C>
-__device__ __forceinline__ void simple_task(const SimpleDesc& D, const typename T::Raw* __restrict__ in,
-                                            void* __restrict__ out, uint32_t g, int lane) {
+__device__ __forceinline__ void simple_task(const SimpleDesc& D, uint32_t g, int lane) {
   using V = typename Chunk<typename T::Raw, C>::V;
+  using Raw = typename T::Raw;
+  const Raw* __restrict__ in = reinterpret_cast<const Raw*>(D.in);
   const int v1 = D.v1;
+  const int v0sh = (int)(D.bits & 0xFFu);
   const int uv1 = lane & (v1 - 1);
-  const int uv0 = (lane >> D.v0sh) & (D.v0 - 1);
+  const int uv0 = (lane >> v0sh) & (D.v0 - 1);
   const bool real = lane < D.v0 * v1;  // lanes beyond both levels' units are idle
   const long long span1 = (long long)v1 * C;
   DevSeg S;
   S.vmask = (uint32_t)(v1 - 1);
-  S.ufast = D.ufast;
+  S.ufast = (D.bits >> 16) & 0x3Fu;
   S.op = HP_OP_SUM;
   for (int s0 = 0; s0 < D.strips0; ++s0) {
     const long long o = ((long long)g * D.v0 + uv0) + (long long)s0 * D.g0 * D.v0;
     const bool valid = o < D.e0;
     const long long sb = (valid ? o : 0) * D.block;  // an invalid lane reads output 0's block
     const long long h = D.flat_b ? ((-sb) & (long long)(C - 1)) : 0;
-    const typename T::Raw* __restrict__ p = in + sb + h + (long long)uv1 * C;
+    const Raw* __restrict__ p = in + sb + h + (long long)uv1 * C;
+    // the rest of a flat block: whole vectors of its tail, then single elements
+    long long tail = 0, nv = 0, ns = 0, tv = 0;
+    V rv[kRestVecPre];
+    Raw r1[kRestOnePre];
+    if (D.flat_b) {
+      tail = sb + h + D.flat_e;
+      const long long tl = D.flat_b - h - D.flat_e;
+      nv = tl / C;
+      ns = h + (tl - nv * C);
+      tv = tail + nv * C;
+#pragma unroll
+      for (int i = 0; i < kRestVecPre; ++i) {
+        const long long j = uv1 + (long long)i * v1;
+        if (j < nv) rv[i] = load_chunk<V>(in + tail + j * C);
+      }
+#pragma unroll
+      for (int i = 0; i < kRestOnePre; ++i) {
+        const long long k = uv1 + (long long)i * v1;
+        if (k < ns) r1[i] = in[k < h ? sb + k : tv + (k - h)];
+      }
+    }
     FAcc a = T::identity(0);
     // the interior: strips1 chunks, four loads in flight
     int f = 0;
@@ -87,20 +116,23 @@ __device__ __forceinline__ void simple_task(const SimpleDesc& D, const typename 
       for (int u = 0; u < 4; ++u) AddChunk<T, C, HP_OP_SUM>::run(a, x[u], 0, true);
     }
     for (; f < D.strips1; ++f) AddChunk<T, C, HP_OP_SUM>::run(a, load_chunk<V>(p + (long long)f * span1), 0, true);
-    if (D.flat_b) {  // the rest of a flat block, in flat_rest's order
-      const long long tail = sb + h + D.flat_e;
-      const long long tl = D.flat_b - h - D.flat_e;
-      const long long nv = tl / C;
-      const long long ns = h + (tl - nv * C);
-      const long long tv = tail + nv * C;
-      for (long long j = uv1; j < nv; j += v1) RestVec<T, C>::run(a, in + tail + j * C, HP_OP_SUM);
-      for (long long k = uv1; k < ns; k += v1) RestAdd<T>::run(a, in[k < h ? sb + k : tv + (k - h)], HP_OP_SUM);
+    if (D.flat_b) {  // in flat_rest's order
+#pragma unroll
+      for (int i = 0; i < kRestVecPre; ++i)
+        if (uv1 + (long long)i * v1 < nv) AddChunk<T, C, HP_OP_SUM>::run(a, rv[i], 0, true);
+      for (long long j = uv1 + (long long)kRestVecPre * v1; j < nv; j += v1)
+        RestVec<T, C>::run(a, in + tail + j * C, HP_OP_SUM);
+#pragma unroll
+      for (int i = 0; i < kRestOnePre; ++i)
+        if (uv1 + (long long)i * v1 < ns) RestAdd<T>::run(a, r1[i], HP_OP_SUM);
+      for (long long k = uv1 + (long long)kRestOnePre * v1; k < ns; k += v1)
+        RestAdd<T>::run(a, in[k < h ? sb + k : tv + (k - h)], HP_OP_SUM);
     }
     a = lane_combine<T>(a, S, lane);
     if (valid && real && uv1 == 0) {
       const double v = (double)a.s + (double)a.c;
-      if (D.out_f64) reinterpret_cast<double*>(out)[o] = v;
-      else reinterpret_cast<float*>(out)[o] = (float)v;
+      if (D.bits & 0x100u) reinterpret_cast<double*>(D.out)[o] = v;
+      else reinterpret_cast<float*>(D.out)[o] = (float)v;
     }
   }
 }
@@ -156,9 +188,7 @@ __device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
     }
     if constexpr (T::kFloat && KD == 4) {
       if (y & kSimpleTask) {
-        simple_task<T, C>(*(const SimpleDesc*)((CSimple*)B.simple + x),
-                          reinterpret_cast<const typename T::Raw*>(B.ins[x]), B.outs[x],
-                          (uint32_t)(y & ~kSimpleTask), lane);
+        simple_task<T, C>(*(const SimpleDesc*)((CSimple*)B.simple + x), (uint32_t)(y & ~kSimpleTask), lane);
         t = u;
         t_end = u_end;
         continue;
