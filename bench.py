@@ -551,14 +551,14 @@ def serving(duration_s=10.0, rate=20000.0, warmup_s=1.0, sweep=True):
     res = serve_stream(pools, duration_s, rate, warmup_s, verify=True)
     if sweep:
         res["rate_sweep"] = []
-        r = 2 * rate
+        r = 1.25 * rate
         while r <= 2.56e6:
             s = serve_stream(pools, 1.5, r, 0.5, verify=False)
             res["rate_sweep"].append({k: s[k] for k in ("offered_rate_per_s", "measured_requests", "all_ok", "p50_us",
                                                         "p99_us", "GBps", "batches")})
             if s["p99_us"] > 1000.0 or not s["all_ok"]:
                 break
-            r *= 2
+            r *= 1.25
     del pools
     return res
 

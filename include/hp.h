@@ -415,6 +415,35 @@ hp_status hp_stencil_destroy(hp_stencil_t s);
  * multiples of 16; asynchronous on `stream`. */
 hp_status hp_stream_read(const void* d_in, size_t bytes, float* d_out, int32_t grid, void* stream);
 
+/* The device's hardware levels and their properties -- the build's analogue of
+ * the paper's Table 2 (section 3.2 selects levels by property).  The automatic
+ * map reads it: a reduction on a level needs a way to combine its units' values,
+ * so reducing levels go first to the level with HP_LP_SHUFFLE (the wavefront's
+ * lanes), then to the level with HP_LP_BARRIER and HP_LP_LOCALMEM (a workgroup's
+ * waves, through LDS), and last to the grid, which has neither (a second kernel
+ * folds its partials); the unit counts bound the lanes and waves it hands out;
+ * `fill_workgroups` is the grid size below which the outermost reducing level is
+ * also split over workgroups.  HP_LP_SHARED_CACHE (an XCD's L2) pays only when
+ * several workgroups read the same data; a nested reduction reads every element
+ * once, so the automatic map never places a level on X (explicit maps may).
+ * hp_level_table copies the rows, outermost first (G, X, W, V, L), into out
+ * (cap rows at most) and sets *n to the number of rows and *fill_workgroups.
+ * Host only.  Errors: HP_EINVAL for null pointers or cap < 1. */
+#define HP_LP_BARRIER 0x1u      /* the level's units can wait for each other */
+#define HP_LP_SHUFFLE 0x2u      /* they exchange registers directly (DPP, permlane, bpermute) */
+#define HP_LP_LOCALMEM 0x4u     /* they share an addressable scratch memory (LDS) */
+#define HP_LP_ATOMIC 0x8u       /* they have atomics on memory they share */
+#define HP_LP_DYNAMIC 0x10u     /* work can be handed to them dynamically (a counter) */
+#define HP_LP_LOCKSTEP 0x20u    /* they run in lockstep */
+#define HP_LP_SHARED_CACHE 0x40u /* they share a cache that is not addressable */
+typedef struct hp_level_props {
+  uint32_t scope;       /* HP_SCOPE_* bit of the level */
+  int32_t units;        /* units inside one unit of the next level out; 0: as many as the work needs */
+  uint32_t props;       /* HP_LP_* bits */
+  int64_t shared_bytes; /* memory the units share: LDS per workgroup, L2 per XCD; 0: none */
+} hp_level_props;
+hp_status hp_level_table(hp_level_props* out, int32_t cap, int32_t* n, int64_t* fill_workgroups);
+
 /* Diagnostic of the XCD scope: launches `grid` workgroups of `threads` threads
  * (a multiple of 64, at most 1024) with `lds_bytes` of dynamic LDS (at most
  * 64 KiB), and thread 0 of workgroup b writes to d_out[b] the XCD it runs on, as

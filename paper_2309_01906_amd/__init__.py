@@ -323,6 +323,30 @@ def stream_read(inp, scratch, grid: int, stream=None):
                                ctypes.c_void_p(scratch.data_ptr()), int(grid), _stream_handle(stream)))
 
 
+class LevelProps(ctypes.Structure):
+    _fields_ = [("scope", ctypes.c_uint32), ("units", ctypes.c_int32), ("props", ctypes.c_uint32),
+                ("shared_bytes", ctypes.c_int64)]
+
+
+LP_BARRIER, LP_SHUFFLE, LP_LOCALMEM, LP_ATOMIC, LP_DYNAMIC, LP_LOCKSTEP, LP_SHARED_CACHE = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40)
+
+
+def level_table():
+    """hp_level_table: the device's hardware levels and their properties (host only).
+    Returns (rows, fill_workgroups); a row is a dict with the scope letter."""
+    L = lib()
+    L.hp_level_table.argtypes = [ctypes.POINTER(LevelProps), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int64)]
+    L.hp_level_table.restype = ctypes.c_int
+    rows = (LevelProps * 8)()
+    n, fill = ctypes.c_int32(), ctypes.c_int64()
+    check(L.hp_level_table(rows, 8, ctypes.byref(n), ctypes.byref(fill)))
+    names = {v: k for k, v in SCOPE.items()}
+    return ([{"scope": names[rows[i].scope], "units": rows[i].units, "props": rows[i].props,
+              "shared_bytes": rows[i].shared_bytes} for i in range(n.value)], fill.value)
+
+
 def xcd_ids(grid: int, threads: int = 256, lds_bytes: int = 0, stream=None):
     """hp_xcd_ids: the XCD that each of `grid` workgroups of `threads` threads runs on,
     as the hardware reports it (int32 device tensor of `grid` entries)."""

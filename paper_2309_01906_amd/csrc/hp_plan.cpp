@@ -56,6 +56,30 @@ static FastDiv fastdiv(uint64_t d) {
   return FastDiv{(uint32_t)m, s};
 }
 
+// gfx950's hardware levels (vendor figures; 256 compute units in 8 XCDs).
+static const hp_level_props kLevels[] = {
+    {HP_SCOPE_G, 0, HP_LP_ATOMIC | HP_LP_DYNAMIC, 0},
+    {HP_SCOPE_X, 8, HP_LP_SHARED_CACHE, 4ll << 20},
+    {HP_SCOPE_W, kMaxWaves, HP_LP_BARRIER | HP_LP_LOCALMEM | HP_LP_ATOMIC | HP_LP_DYNAMIC, 64ll << 10},
+    {HP_SCOPE_V, kWave, HP_LP_SHUFFLE | HP_LP_LOCKSTEP, 0},
+    {HP_SCOPE_L, 0, 0, 0},
+};
+static constexpr int kLevelRows = (int)(sizeof kLevels / sizeof kLevels[0]);
+static constexpr int64_t kFillWorkgroups = 256 * 8;  // compute units x 8
+
+static const hp_level_props& level_of(uint32_t scope) {
+  for (const hp_level_props& l : kLevels)
+    if (l.scope == scope) return l;
+  return kLevels[kLevelRows - 1];
+}
+// the innermost level that offers `need` (all bits) among the wavefront, workgroup
+// and grid: where a reduction's units can be combined
+static uint32_t combine_scope(uint32_t need) {
+  for (int i = kLevelRows - 1; i >= 0; --i)
+    if ((kLevels[i].props & need) == need && kLevels[i].scope != HP_SCOPE_L) return kLevels[i].scope;
+  return HP_SCOPE_G;
+}
+
 // Automatic map: NONE levels on the grid; reducing levels fill the lanes of a
 // wavefront from the innermost level outward (shuffles are the cheapest combine),
 // then the waves of a workgroup (LDS + barrier), then, when the outputs alone do
@@ -112,8 +136,10 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
       return;
     }
   }
-  // lanes of one wavefront, innermost reducing level first
-  int lanes_left = kWave;
+  // lanes of one wavefront, innermost reducing level first: the level whose units
+  // shuffle registers (the cheapest combine, section 2)
+  const uint32_t v_scope = combine_scope(HP_LP_SHUFFLE);
+  int lanes_left = level_of(v_scope).units;
   int l = d - 1;
   int first_v = d;
   while (l >= p && lanes_left > 1) {
@@ -128,7 +154,7 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
       if ((arg || a != b) && f >= 4) f /= 4;
     }
     if (f >= (uint64_t)lanes_left || l == p) f = (uint64_t)lanes_left;
-    m->scopes[l] = HP_SCOPE_V;
+    m->scopes[l] = v_scope;
     m->units[l][HP_AXIS_V] = (uint32_t)f;
     lanes_left /= (int)f;
     first_v = l;
@@ -137,22 +163,25 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
   if (lanes_left > 1) m->units[first_v][HP_AXIS_V] *= (uint32_t)lanes_left;
   const uint64_t nw_target = bytes >= (256 << 10) ? 8 : bytes >= (16 << 10) ? 4 : bytes >= (4 << 10) ? 2 : 1;
   // waves of one workgroup: the next level outward, or the outermost lane level
+  // the next level out whose units combine through a barrier and shared memory
+  const uint32_t w_scope = combine_scope(HP_LP_BARRIER | HP_LP_LOCALMEM);
   int w_level;
   int64_t per_wave_unit;
   if (l >= p) {
     w_level = l;
-    m->scopes[l] = HP_SCOPE_W;
+    m->scopes[l] = w_scope;
     per_wave_unit = n->extent[l];
     --l;
   } else {
     w_level = first_v;
-    m->scopes[first_v] |= HP_SCOPE_W;
+    m->scopes[first_v] |= w_scope;
     per_wave_unit = cdiv(cdiv(n->extent[first_v], first_v == d - 1 ? chunk_last : 1),
                          m->units[first_v][HP_AXIS_V]);
   }
   {
     uint64_t f = pow2ceil((uint64_t)per_wave_unit);
     if (f > nw_target) f = nw_target;
+    if (f > (uint64_t)level_of(w_scope).units) f = (uint64_t)level_of(w_scope).units;
     if (force_nw > 0) f = (uint64_t)force_nw;
     m->units[w_level][HP_AXIS_W] = (uint32_t)f;
   }
@@ -162,7 +191,7 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
   if (l < p) {
     int64_t n_out = 1;
     for (int k = 0; k < p; ++k) n_out *= n->extent[k];
-    const int64_t target_wgs = 2048;
+    const int64_t target_wgs = kFillWorkgroups;
     if (n_out < target_wgs) {
       const int64_t per = p == d - 1 ? cdiv(n->extent[p], chunk_last) : n->extent[p];
       const int64_t in_wg = (int64_t)(m->units[p][HP_AXIS_V] ? m->units[p][HP_AXIS_V] : 1) *
@@ -306,6 +335,19 @@ int64_t flat_interior(int64_t b, int c, int64_t unit) {
   const int64_t hmax = (b % c) ? c - 1 : 0;
   return (b - hmax) / unit * unit;
 }
+
+}  // namespace hp
+
+extern "C" hp_status hp_level_table(hp_level_props* out, int32_t cap, int32_t* n, int64_t* fill_workgroups) {
+  if (!out || !n || !fill_workgroups || cap < 1) return hp::fail(HP_EINVAL, "null pointer or cap < 1");
+  const int k = cap < hp::kLevelRows ? cap : hp::kLevelRows;
+  for (int i = 0; i < k; ++i) out[i] = hp::kLevels[i];
+  *n = hp::kLevelRows;
+  *fill_workgroups = hp::kFillWorkgroups;
+  return HP_OK;
+}
+
+namespace hp {
 
 hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out, int force_nw,
                 int64_t flat_block) {

@@ -280,3 +280,48 @@ def test_int_kernel_choice():
     assert hp.inspect((64, 128, 64), ("NONE", "ARGMIN", "SUM"), hp.I32)["kernel"] == hp.KERNEL_INT_DEEP
     assert hp.inspect((64, 128, 64), ("NONE", "ARGMIN", "MAX"), hp.I32)["kernel"] == hp.KERNEL_INT_CHAIN
     assert hp.inspect((64, 128, 64, 64), ("NONE", "SUM", "SUM", "MAX"), hp.I32)["kernel"] == hp.KERNEL_INT_SEG
+
+
+def test_level_table_and_automatic_maps_follow_it():
+    """The level-property table (the analogue of the paper's Table 2) and the automatic
+    map's choices: a reducing level's lanes are on the level that shuffles, its waves on
+    the level with a barrier and shared memory, the grid (no barrier) only through a
+    fold; lanes and waves within the table's unit counts; the outermost reducing level
+    split over the grid only when the outputs alone give fewer workgroups than the
+    table's fill target; and never the XCD level (its shared cache pays only for data
+    read more than once)."""
+    rows, fill = hp.level_table()
+    by = {r["scope"]: r for r in rows}
+    assert [r["scope"] for r in rows] == ["G", "X", "W", "V", "L"]
+    assert by["V"]["props"] & hp.LP_SHUFFLE and by["V"]["units"] == 64
+    assert by["W"]["props"] & hp.LP_BARRIER and by["W"]["props"] & hp.LP_LOCALMEM and by["W"]["units"] == 16
+    assert not by["G"]["props"] & (hp.LP_BARRIER | hp.LP_SHUFFLE) and by["X"]["units"] == 8
+    assert fill == 2048
+    rng = np.random.default_rng(5)
+    checked = 0
+    for _ in range(300):
+        depth = int(rng.integers(2, 5))
+        ext = tuple(int(x) for x in rng.integers(1, 300, size=depth))
+        p = int(rng.integers(0, depth))
+        ops = ["NONE"] * p + [str(rng.choice(["SUM", "MIN", "MAX", "ARGMIN"])) for _ in range(depth - p)]
+        try:
+            i = hp.inspect(ext, ops, hp.I32)
+        except hp.HPError:
+            continue
+        if i["flat_block"]:
+            continue
+        checked += 1
+        n_out = int(np.prod(ext[:p])) if p else 1
+        lanes = waves = 1
+        for lvl in range(i["depth"]):
+            sc = i["map"][lvl]
+            assert "X" not in sc, (ext, ops, i["map"])
+            g, w, v = i["units"][lvl]
+            lanes *= v
+            waves *= w
+            # one or two reducing levels fit a workgroup's lanes and waves: one on the
+            # grid as well is only ever a split to fill the chip
+            if lvl >= p and g > 1 and depth - p <= 2:
+                assert n_out < fill and i["gsplit"] > 1, (ext, ops, i["map"], i["units"])
+        assert lanes <= by["V"]["units"] and waves <= by["W"]["units"], (ext, ops, i["units"])
+    assert checked > 150
