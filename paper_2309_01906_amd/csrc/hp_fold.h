@@ -50,10 +50,18 @@ __device__ __forceinline__ double fold_flt_seq(const char* part, long long G) {
 // whole wave; every lane returns the result
 __device__ __forceinline__ double fold_flt_wave(const char* part, long long G, int lane) {
   DPair a{0.0, 0.0};
-  for (long long k = lane; k < G; k += kWave) {
-    const FAcc v = FloatT<float>::get(part, k);
-    dpair_add(a, (double)v.s);
-    dpair_add(a, (double)v.c);
+  constexpr int B = kFoldBatch / 2;
+  for (long long k0 = lane; k0 < G; k0 += (long long)B * kWave) {
+    FAcc v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + (long long)u * kWave < G) v[u] = FloatT<float>::get(part, k0 + (long long)u * kWave);
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + (long long)u * kWave < G) {
+        dpair_add(a, (double)v[u].s);
+        dpair_add(a, (double)v[u].c);
+      }
   }
 #pragma unroll
   for (int b = 0; b < 6; ++b) {
