@@ -356,11 +356,12 @@ def ordered_products(stream, steps=20, warmup=3):
 
 
 def stencils(stream, steps=20, warmup=3):
-    """Five-point Jacobi sweeps of an 8192 x 8192 fp32 array (256 MiB), 1, 4 and 8
-    sweeps per launch, tiled through LDS with a ghost surface.  `effective_GBps`
-    counts one read and one write of every cell per sweep (what separate sweeps
-    would move); `hbm_GBps` counts what one launch moves: the 32 x 64 tiles with
-    their ghost cells read once, the array written once."""
+    """Five-point Jacobi sweeps of an 8192 x 8192 fp32 array (256 MiB): 1, 4 and 8
+    sweeps in one launch and 16 in two, tiled through LDS with a ghost surface, the
+    tiles dealt to the XCDs in bands; 1 and 8 sweeps also without the XCD bands.
+    `effective_GBps` counts one read and one write of every cell per sweep (what
+    separate sweeps would move); `hbm_GBps` counts what the launches move: each tile
+    with its ghost cells read once, the array written once."""
     import torch
 
     import paper_2309_01906_amd as hp
@@ -369,8 +370,8 @@ def stencils(stream, steps=20, warmup=3):
     x = torch.from_numpy(workloads.normal_f32(230901906 + 7, (R, C))).cuda()
     y = torch.empty_like(x)
     res = {}
-    for t in (1, 4, 8):
-        with hp.Stencil(R, C, t, 0.6, 0.1) as st:
+    for t, flags in ((1, 0), (4, 0), (8, 0), (16, 0), (1, hp.STENCIL_NO_XCD), (8, hp.STENCIL_NO_XCD)):
+        with hp.Stencil(R, C, t, 0.6, 0.1, flags=flags) as st:
             for _ in range(warmup):
                 st.run(x, y, stream)
             torch.cuda.synchronize()
@@ -382,11 +383,14 @@ def stencils(stream, steps=20, warmup=3):
                 e_.record(stream)
                 e_.synchronize()
                 ev.append(s_.elapsed_time(e_))
+            inf = st.info
         us = pct(ev, 50) * 1e3
-        amp = (32 + 2 * t) * (64 + 2 * t) / (32 * 64)
-        res[f"sweeps_{t}"] = {"p50_us": round(us, 1),
-                              "effective_GBps": round(8.0 * R * C * t / us / 1e3, 1),
-                              "hbm_GBps": round((4.0 * amp + 4.0) * R * C / us / 1e3, 1)}
+        th, tw, per = inf["tile_rows"], inf["tile_cols"], inf["sweeps_per_launch"]
+        amp = (th + 2 * per) * (tw + 2 * per) / (th * tw)
+        key = f"sweeps_{t}" + ("_no_xcd" if flags else "")
+        res[key] = {"p50_us": round(us, 1), "tile": [th, tw], "launches": inf["launches"],
+                    "effective_GBps": round(8.0 * R * C * t / us / 1e3, 1),
+                    "hbm_GBps": round(inf["launches"] * (4.0 * amp + 4.0) * R * C / us / 1e3, 1)}
     del x, y
     return res
 

@@ -393,15 +393,36 @@ hp_status hp_server_destroy(hp_server_t s);
  * `steps` five-point Jacobi sweeps of a rows x cols row-major float array,
  *   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1]))
  * for 1 <= i <= rows-2, 1 <= j <= cols-2 (fp32, in exactly this order, no fused
- * multiply-add); boundary cells keep their values.  Every workgroup reads its
- * 32 x 64 output tile plus a ghost surface `steps` cells wide into LDS once, runs
- * all sweeps there and writes the tile once.
- * hp_stencil_plan: rows, cols >= 1 (HP_EINVAL), 1 <= steps <= 8 (HP_EUNSUPPORTED).
+ * multiply-add); boundary cells keep their values.  Levels: each workgroup reads a
+ * tile_rows x 64 output tile plus a ghost surface T cells wide into LDS once, runs
+ * T sweeps there and writes the tile once; each lane updates column strips of 4
+ * cells from registers; the tiles are dealt to the XCDs in bands, so ghost cells
+ * that neighbouring tiles share come from HBM once into the XCD's L2.  More sweeps
+ * than one launch holds (8) run as ceil(steps / T) launches, alternating between
+ * d_out and a rows x cols buffer the plan allocates, so that the last writes d_out.
+ * hp_stencil_plan: rows, cols >= 1, steps >= 1 (HP_EINVAL); 32-row tiles and at
+ *   most 8 sweeps per launch, spread evenly over the launches; the tile must fit
+ *   the workgroup level's local memory (hp_level_table).
+ * hp_stencil_plan_ex: the same with tile_rows (0: choose, 32 or 64), sweeps per
+ *   launch (0: choose, 1..8) and flags (HP_STENCIL_NO_XCD: tile b on workgroup b);
+ *   HP_EINVAL for other values, HP_EUNSUPPORTED when the tile does not fit LDS or
+ *   the array needs more tiles than one launch holds.  The plan remembers the
+ *   current device when it allocates its buffer; run it there (HP_EINVAL).
+ * hp_stencil_info: the tile rows and columns, sweeps per launch and launches.
  * hp_stencil_run: d_in and d_out are caller-owned device arrays of rows*cols
- * floats, 4-byte aligned, not overlapping (HP_EINVAL); asynchronous on `stream`.
+ *   floats, 4-byte aligned, not overlapping (HP_EINVAL); asynchronous on `stream`.
+ *   Calls that share a plan of several launches must not overlap (they share its
+ *   buffer).
+ * hp_stencil_destroy frees the plan and its buffer (call it once the plan's last
+ *   run has finished); NULL is a no-op.
  */
+enum { HP_STENCIL_NO_XCD = 1 };
 typedef struct hp_stencil_s* hp_stencil_t;
 hp_status hp_stencil_plan(int64_t rows, int64_t cols, int32_t steps, float c0, float c1, hp_stencil_t* out);
+hp_status hp_stencil_plan_ex(int64_t rows, int64_t cols, int32_t steps, float c0, float c1, int32_t tile_rows,
+                             int32_t sweeps_per_launch, uint32_t flags, hp_stencil_t* out);
+hp_status hp_stencil_info(hp_stencil_t s, int32_t* tile_rows, int32_t* tile_cols, int32_t* sweeps_per_launch,
+                          int32_t* launches);
 hp_status hp_stencil_run(hp_stencil_t s, const float* d_in, float* d_out, void* stream);
 hp_status hp_stencil_destroy(hp_stencil_t s);
 

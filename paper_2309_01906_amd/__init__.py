@@ -276,19 +276,30 @@ class Plan:
         self.close()
 
 
+STENCIL_NO_XCD = 1
+
+
 class Stencil:
     """`steps` five-point Jacobi sweeps of a 2-D float32 device array, tiled through
-    LDS with a ghost surface (hp_stencil_*)."""
+    LDS with a ghost surface (hp_stencil_*).  tile_rows (32 or 64) and
+    sweeps_per_launch (1..8) default to the plan's choice; `info` holds what it chose."""
 
-    def __init__(self, rows: int, cols: int, steps: int, c0: float, c1: float):
+    def __init__(self, rows: int, cols: int, steps: int, c0: float, c1: float, tile_rows: int = 0,
+                 sweeps_per_launch: int = 0, flags: int = 0):
         L = lib()
-        L.hp_stencil_plan.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
-                                      ctypes.POINTER(ctypes.c_void_p)]
+        L.hp_stencil_plan_ex.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+        L.hp_stencil_info.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4
         L.hp_stencil_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.hp_stencil_destroy.argtypes = [ctypes.c_void_p]
         self._h = ctypes.c_void_p()
         self.shape = (int(rows), int(cols))
-        check(L.hp_stencil_plan(int(rows), int(cols), int(steps), float(c0), float(c1), ctypes.byref(self._h)))
+        check(L.hp_stencil_plan_ex(int(rows), int(cols), int(steps), float(c0), float(c1), int(tile_rows),
+                                   int(sweeps_per_launch), int(flags), ctypes.byref(self._h)))
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(L.hp_stencil_info(self._h, *[ctypes.byref(x) for x in v]))
+        self.info = dict(zip(("tile_rows", "tile_cols", "sweeps_per_launch", "launches"), (x.value for x in v)))
 
     def run(self, inp, out=None, stream=None):
         torch = _torch()

@@ -2,39 +2,105 @@
 // algorithms, section 2, and its ghost surfaces, section 4): `steps` five-point
 // Jacobi sweeps of a 2-D float array with fixed boundary cells,
 //   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1])).
-// Each workgroup owns a TH x TW output tile.  It reads the tile plus a ghost
-// surface `steps` cells wide into LDS once, runs all sweeps there -- the valid
-// region shrinks by one cell per sweep -- and writes the tile once: HBM sees one
-// read and one write per cell for `steps` sweeps, plus the ghost cells.
+// The tiling is repeated on the levels that have local memory: each workgroup owns a
+// TH x 64 output tile in LDS (the workgroup level), each lane a column strip of 4
+// cells in registers (the lane level).  A launch reads the tile plus a ghost surface
+// T cells wide into LDS once, runs T sweeps there -- the valid region shrinks by one
+// cell per sweep -- and writes the tile once: HBM sees one read and one write per
+// cell for T sweeps, plus the ghost cells.  The tiles are dealt to the XCDs in
+// bands, so that the ghost cells neighbouring tiles share come from HBM once into
+// the XCD's L2 (the X level's shared cache).  The plan checks the tile against the
+// workgroup level's local memory in the level-property table; more sweeps than one
+// launch holds run as several launches through a buffer the plan owns.
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <type_traits>
 
 #include "hp_internal.h"
 
 namespace hp {
 
-constexpr int kTH = 32;  // output rows per workgroup
 constexpr int kTW = 64;  // output columns per workgroup
 constexpr int kThreads = 256;
+constexpr int kMaxSweeps = 8;  // sweeps one launch can hold (kernels are instantiated up to this)
 
-template <int T>
+template <int T, int TH>
 struct Tile {
-  static constexpr int H = kTH + 2 * T;  // rows in LDS (with the ghost surface)
+  static constexpr int H = TH + 2 * T;   // rows in LDS (with the ghost surface)
   static constexpr int W = kTW + 2 * T;  // columns in LDS
   static constexpr int P = W + 1;        // row pitch (odd: neighbouring rows in different banks)
   static constexpr int kFloats = H * P;
 };
 
-template <int T>
+// LDS bytes of a tile of th output rows and t sweeps (two ping-pong buffers)
+static size_t tile_lds_bytes(int th, int t) {
+  return 2u * (size_t)(th + 2 * t) * (size_t)(kTW + 2 * t + 1) * sizeof(float);
+}
+
+// One sweep over the region still valid after sweep S, in column strips of kRB
+// cells: a thread reads kRB + 2 cells of its column and kRB of each neighbouring
+// column for kRB updates, instead of 5 reads per update.  EDGE: the tile touches the
+// array's boundary, so each cell is tested against the interior range; an interior
+// tile (every workgroup but those on the array's rim) skips the tests.
+template <int S, int H, int W, int PITCH, bool EDGE>
+__device__ __forceinline__ void sweep(const float* __restrict__ src, float* __restrict__ dst, int tid, float c0,
+                                      float c1, int ilo, int ihi, int jlo, int jhi) {
+  constexpr int kRB = 4;
+  constexpr int wr = W - 2 * S;
+  constexpr int hr = H - 2 * S;
+  constexpr int nfull = hr / kRB;  // strips of kRB whole rows
+  constexpr int rem = hr - nfull * kRB;
+  constexpr int n = (nfull + (rem ? 1 : 0)) * wr;
+  for (int k = tid; k < n; k += kThreads) {
+    const int rb = k / wr;
+    const int c = S + (k - rb * wr);
+    const int r0 = S + rb * kRB;
+    const bool col_in = !EDGE || (c >= jlo && c <= jhi);
+    const float* q0 = src + r0 * PITCH + c;
+    float* d0 = dst + r0 * PITCH + c;
+    float up = q0[-PITCH];
+    float mid = q0[0];
+    const int rows = (rem && rb == nfull) ? rem : kRB;
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      if (d < rows) {
+        const float dn = q0[(d + 1) * PITCH];
+        float v = c0 * mid + c1 * ((up + dn) + (q0[d * PITCH - 1] + q0[d * PITCH + 1]));
+        if (EDGE && !(col_in && r0 + d >= ilo && r0 + d <= ihi)) v = mid;
+        d0[d * PITCH] = v;
+        up = mid;
+        mid = dn;
+      }
+    }
+  }
+}
+
+// The tile a workgroup works on.  Workgroup b runs on the XCD b mod 8 selects (the
+// dispatcher deals consecutive workgroups round-robin over the 8 XCDs, from a start
+// that varies between launches, so the workgroups sharing b mod 8 share an XCD);
+// those workgroups take one contiguous run of tiles in row-major tile order -- a band
+// of the array -- so the ghost cells that neighbouring tiles both read are fetched
+// from HBM once into that XCD's L2 (the shared cache of the X level).  Without XCD
+// dealing, tile = b.
+__device__ __forceinline__ uint32_t stencil_tile(uint32_t b, uint32_t nt, bool xcd) {
+  if (!xcd) return b;
+  const uint32_t x = b & 7u, k = b >> 3, q = nt >> 3, r = nt & 7u;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <int T, int TH>
 __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ in, float* __restrict__ out,
-                                                      long long R, long long C, float c0, float c1) {
-  using G = Tile<T>;
+                                                      long long R, long long C, uint32_t ntc, uint32_t nt, int xcd,
+                                                      float c0, float c1) {
+  using G = Tile<T, TH>;
   extern __shared__ float lds[];
   float* buf0 = lds;
   float* buf1 = lds + G::kFloats;
-  const long long i0 = (long long)blockIdx.y * kTH - T;  // global row of LDS row 0
-  const long long j0 = (long long)blockIdx.x * kTW - T;  // global column of LDS column 0
+  const uint32_t tile = stencil_tile(blockIdx.x, nt, xcd != 0);
+  const uint32_t ty = tile / ntc, tx = tile - ty * ntc;
+  const long long i0 = (long long)ty * TH - T;   // global row of LDS row 0
+  const long long j0 = (long long)tx * kTW - T;  // global column of LDS column 0
   const int tid = (int)threadIdx.x;
   // the tile and its ghost surface; cells outside the array are never read by an
   // updated cell (only interior cells change, and their neighbours are inside)
@@ -63,74 +129,119 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
   };
   const int ilo = local(1, i0, G::H), ihi = local(R - 2, i0, G::H);
   const int jlo = local(1, j0, G::W), jhi = local(C - 2, j0, G::W);
-#pragma unroll
-  for (int s = 1; s <= T; ++s) {
-    const float* src = (s & 1) ? buf0 : buf1;
-    float* dst = (s & 1) ? buf1 : buf0;
-    // the region still valid after sweep s, in column strips of kRB cells: a thread
-    // reads kRB + 2 cells of its column and kRB of each neighbouring column for kRB
-    // updates, instead of 5 reads per update
-    constexpr int kRB = 4;
-    const int wr = G::W - 2 * s;
-    const int hr = G::H - 2 * s;
-    const int n = ((hr + kRB - 1) / kRB) * wr;
-    for (int k = tid; k < n; k += kThreads) {
-      const int rb = k / wr;
-      const int c = s + (k - rb * wr);
-      const int r0 = s + rb * kRB;
-      const bool col_in = c >= jlo && c <= jhi;
-      float up = src[(r0 - 1) * G::P + c];
-      float mid = src[r0 * G::P + c];
-#pragma unroll
-      for (int d = 0; d < kRB; ++d) {
-        const int r = r0 + d;
-        if (r < s + hr) {
-          const int q = r * G::P + c;
-          const float dn = src[q + G::P];
-          float v = mid;
-          if (col_in && r >= ilo && r <= ihi) v = c0 * mid + c1 * ((up + dn) + (src[q - 1] + src[q + 1]));
-          dst[q] = v;
-          up = mid;
-          mid = dn;
-        }
-      }
-    }
+  // every cell any sweep updates is interior: rows 1..H-2 and columns 1..W-2 of the tile
+  const bool edge = !(ilo <= 1 && ihi >= G::H - 2 && jlo <= 1 && jhi >= G::W - 2);
+  auto run = [&](auto S_) {
+    constexpr int S = decltype(S_)::value;
+    const float* src = (S & 1) ? buf0 : buf1;
+    float* dst = (S & 1) ? buf1 : buf0;
+    if (edge) sweep<S, G::H, G::W, G::P, true>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
+    else sweep<S, G::H, G::W, G::P, false>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
     __syncthreads();
-  }
+  };
+  static_assert(T >= 1 && T <= kMaxSweeps, "sweeps per launch");
+  run(std::integral_constant<int, 1>{});
+  if constexpr (T >= 2) run(std::integral_constant<int, 2>{});
+  if constexpr (T >= 3) run(std::integral_constant<int, 3>{});
+  if constexpr (T >= 4) run(std::integral_constant<int, 4>{});
+  if constexpr (T >= 5) run(std::integral_constant<int, 5>{});
+  if constexpr (T >= 6) run(std::integral_constant<int, 6>{});
+  if constexpr (T >= 7) run(std::integral_constant<int, 7>{});
+  if constexpr (T >= 8) run(std::integral_constant<int, 8>{});
   const float* fin = (T & 1) ? buf1 : buf0;
-  for (int k = tid; k < kTH * kTW; k += kThreads) {
+  for (int k = tid; k < TH * kTW; k += kThreads) {
     const int r = T + k / kTW, c = T + (k - (k / kTW) * kTW);
     const long long gi = i0 + r, gj = j0 + c;
     if (gi < R && gj < C) out[gi * C + gj] = fin[r * G::P + c];
   }
 }
 
-template <int T>
-hp_status launch_t(const float* in, float* out, long long R, long long C, float c0, float c1, hipStream_t st) {
-  const dim3 grid((unsigned)((C + kTW - 1) / kTW), (unsigned)((R + kTH - 1) / kTH));
-  hipLaunchKernelGGL(k_stencil<T>, grid, dim3(kThreads), 2 * Tile<T>::kFloats * sizeof(float), st, in, out, R, C, c0, c1);
+template <int T, int TH>
+hp_status launch_t(const float* in, float* out, long long R, long long C, bool xcd, float c0, float c1,
+                   hipStream_t st) {
+  const uint32_t ntc = (uint32_t)((C + kTW - 1) / kTW), ntr = (uint32_t)((R + TH - 1) / TH);
+  const uint32_t nt = ntc * ntr;
+  constexpr size_t lds = 2 * Tile<T, TH>::kFloats * sizeof(float);
+  hipLaunchKernelGGL((k_stencil<T, TH>), dim3(nt), dim3(kThreads), lds, st, in, out, R, C, ntc, nt, xcd ? 1 : 0, c0,
+                     c1);
   if (hipGetLastError() != hipSuccess) return hp::fail(HP_EDEVICE, "stencil launch failed");
   return HP_OK;
 }
 
+template <int TH>
+hp_status launch_th(int t, const float* in, float* out, long long R, long long C, bool xcd, float c0, float c1,
+                    hipStream_t st) {
+  switch (t) {
+    case 1: return launch_t<1, TH>(in, out, R, C, xcd, c0, c1, st);
+    case 2: return launch_t<2, TH>(in, out, R, C, xcd, c0, c1, st);
+    case 3: return launch_t<3, TH>(in, out, R, C, xcd, c0, c1, st);
+    case 4: return launch_t<4, TH>(in, out, R, C, xcd, c0, c1, st);
+    case 5: return launch_t<5, TH>(in, out, R, C, xcd, c0, c1, st);
+    case 6: return launch_t<6, TH>(in, out, R, C, xcd, c0, c1, st);
+    case 7: return launch_t<7, TH>(in, out, R, C, xcd, c0, c1, st);
+    default: return launch_t<8, TH>(in, out, R, C, xcd, c0, c1, st);
+  }
+}
+
 }  // namespace hp
 
-using hp::kTH;
 using hp::kTW;
 
 struct hp_stencil_s {
   long long rows, cols;
   int steps;
   float c0, c1;
+  int tile_rows;     // output rows per workgroup tile (32 or 64)
+  bool xcd;          // tiles dealt to XCDs in bands
+  int per_launch;    // sweeps per launch (1..8)
+  int launches;      // ceil(steps / per_launch); the last launch takes the remainder
+  float* tmp;        // rows x cols buffer for the intermediate launches (null for one launch)
+  int device;
 };
 
-extern "C" hp_status hp_stencil_plan(int64_t rows, int64_t cols, int32_t steps, float c0, float c1, hp_stencil_t* out) {
+extern "C" hp_status hp_stencil_plan_ex(int64_t rows, int64_t cols, int32_t steps, float c0, float c1,
+                                        int32_t tile_rows, int32_t sweeps_per_launch, uint32_t flags,
+                                        hp_stencil_t* out) {
   if (!out) return hp::fail(HP_EINVAL, "null output handle");
   *out = nullptr;
   if (rows < 1 || cols < 1) return hp::fail(HP_EINVAL, "array %lld x %lld is empty", (long long)rows, (long long)cols);
-  if (steps < 1 || steps > 8) return hp::fail(HP_EUNSUPPORTED, "steps %d outside [1, 8]", steps);
-  if ((rows + kTH - 1) / kTH > 65535 || (cols + kTW - 1) / kTW > 2147483647LL || rows > (int64_t(1) << 62) / cols)
-    return hp::fail(HP_EUNSUPPORTED, "array too large for one launch");
+  if (steps < 1) return hp::fail(HP_EINVAL, "steps %d < 1", steps);
+  if (tile_rows != 0 && tile_rows != 32 && tile_rows != 64)
+    return hp::fail(HP_EINVAL, "tile rows %d: 0 (choose), 32 or 64", tile_rows);
+  if (flags & ~(uint32_t)HP_STENCIL_NO_XCD) return hp::fail(HP_EINVAL, "unknown stencil flags 0x%x", flags);
+  if (sweeps_per_launch < 0 || sweeps_per_launch > hp::kMaxSweeps)
+    return hp::fail(HP_EINVAL, "sweeps per launch %d outside [0, %d]", sweeps_per_launch, hp::kMaxSweeps);
+  // the workgroup level's local memory, from the level-property table
+  hp_level_props lv[8];
+  int32_t nl = 0;
+  int64_t fill = 0;
+  if (hp_level_table(lv, 8, &nl, &fill) != HP_OK) return HP_EDEVICE;
+  int64_t lds = 0;
+  for (int i = 0; i < nl && i < 8; ++i)
+    if (lv[i].scope == HP_SCOPE_W) lds = lv[i].shared_bytes;
+  // Sweeps per launch: as many as a launch holds, spread evenly over the launches
+  // (each launch is one HBM round trip; the wider ghost surface of more sweeps per
+  // launch costs less than a round trip up to 8: 16 sweeps of an 8192 x 8192 array
+  // run as 2 launches of 8 in 0.85x the time of 4 launches of 4).
+  int t = sweeps_per_launch;
+  if (t == 0) {
+    const int k = (steps + hp::kMaxSweeps - 1) / hp::kMaxSweeps;
+    t = (steps + k - 1) / k;
+  }
+  // Tile rows: a 64-row tile reads 17% fewer ghost cells and recomputes fewer of
+  // them at 8 sweeps, but its buffers leave room for 3 workgroups per CU instead of 5;
+  // on an 8192 x 8192 array the 32-row tile is faster at every sweep count (1 to 8),
+  // so it is the default and the taller one is there on request.  Either must fit
+  // the workgroup's local memory.
+  const int th = tile_rows ? tile_rows : 32;
+  if ((int64_t)hp::tile_lds_bytes(th, t) > lds)
+    return hp::fail(HP_EUNSUPPORTED, "a %d-row tile with %d sweeps needs %zu bytes of LDS", th, t,
+                    hp::tile_lds_bytes(th, t));
+  // one workgroup per tile, and a launch holds at most 2^32 - 1 work-items
+  const int64_t max_tiles = (int64_t)(0xFFFFFFFFu / (uint32_t)hp::kThreads);
+  if (rows > (int64_t(1) << 62) / cols || (rows + th - 1) / th > max_tiles / ((cols + kTW - 1) / kTW))
+    return hp::fail(HP_EUNSUPPORTED, "array of %lld x %lld cells needs more tiles than a launch holds",
+                    (long long)rows, (long long)cols);
   hp_stencil_s* s = new (std::nothrow) hp_stencil_s;
   if (!s) return hp::fail(HP_ENOMEM, "host allocation failed");
   s->rows = rows;
@@ -138,7 +249,37 @@ extern "C" hp_status hp_stencil_plan(int64_t rows, int64_t cols, int32_t steps, 
   s->steps = steps;
   s->c0 = c0;
   s->c1 = c1;
+  s->tile_rows = th;
+  s->xcd = !(flags & HP_STENCIL_NO_XCD);
+  s->per_launch = t;
+  s->launches = (steps + t - 1) / t;
+  s->tmp = nullptr;
+  s->device = -1;
+  if (s->launches > 1) {
+    if (hipGetDevice(&s->device) != hipSuccess) {
+      delete s;
+      return hp::fail(HP_EDEVICE, "no HIP device");
+    }
+    if (hipMalloc(&s->tmp, (size_t)rows * (size_t)cols * sizeof(float)) != hipSuccess) {
+      delete s;
+      return hp::fail(HP_ENOMEM, "stencil buffer of %lld x %lld floats", (long long)rows, (long long)cols);
+    }
+  }
   *out = s;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_stencil_plan(int64_t rows, int64_t cols, int32_t steps, float c0, float c1, hp_stencil_t* out) {
+  return hp_stencil_plan_ex(rows, cols, steps, c0, c1, 0, 0, 0, out);
+}
+
+extern "C" hp_status hp_stencil_info(hp_stencil_t s, int32_t* tile_rows, int32_t* tile_cols, int32_t* sweeps_per_launch,
+                                     int32_t* launches) {
+  if (!s || !tile_rows || !tile_cols || !sweeps_per_launch || !launches) return hp::fail(HP_EINVAL, "null argument");
+  *tile_rows = s->tile_rows;
+  *tile_cols = kTW;
+  *sweeps_per_launch = s->per_launch;
+  *launches = s->launches;
   return HP_OK;
 }
 
@@ -148,21 +289,33 @@ extern "C" hp_status hp_stencil_run(hp_stencil_t s, const float* d_in, float* d_
   const uintptr_t bytes = (uintptr_t)(s->rows * s->cols) * sizeof(float);
   if (a < b + bytes && b < a + bytes) return hp::fail(HP_EINVAL, "input and output overlap");
   if ((a & 3u) || (b & 3u)) return hp::fail(HP_EINVAL, "arrays must be 4-byte aligned");
+  if (s->launches > 1) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
+      return hp::fail(HP_EINVAL, "stencil plan was made on device %d, current device is %d", s->device, dev);
+  }
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const long long R = s->rows, C = s->cols;
-  switch (s->steps) {
-    case 1: return hp::launch_t<1>(d_in, d_out, R, C, s->c0, s->c1, st);
-    case 2: return hp::launch_t<2>(d_in, d_out, R, C, s->c0, s->c1, st);
-    case 3: return hp::launch_t<3>(d_in, d_out, R, C, s->c0, s->c1, st);
-    case 4: return hp::launch_t<4>(d_in, d_out, R, C, s->c0, s->c1, st);
-    case 5: return hp::launch_t<5>(d_in, d_out, R, C, s->c0, s->c1, st);
-    case 6: return hp::launch_t<6>(d_in, d_out, R, C, s->c0, s->c1, st);
-    case 7: return hp::launch_t<7>(d_in, d_out, R, C, s->c0, s->c1, st);
-    default: return hp::launch_t<8>(d_in, d_out, R, C, s->c0, s->c1, st);
+  // launch j reads the previous launch's result; the last one writes d_out, and
+  // counting back from it the launches alternate between d_out and the plan's buffer
+  const float* src = d_in;
+  int left = s->steps;
+  for (int j = 0; j < s->launches; ++j) {
+    const int t = left < s->per_launch ? left : s->per_launch;
+    float* dst = ((s->launches - 1 - j) % 2 == 0) ? d_out : s->tmp;
+    const hp_status r = s->tile_rows == 64 ? hp::launch_th<64>(t, src, dst, R, C, s->xcd, s->c0, s->c1, st)
+                                           : hp::launch_th<32>(t, src, dst, R, C, s->xcd, s->c0, s->c1, st);
+    if (r != HP_OK) return r;
+    src = dst;
+    left -= t;
   }
+  return HP_OK;
 }
 
 extern "C" hp_status hp_stencil_destroy(hp_stencil_t s) {
+  if (!s) return HP_OK;
+  hp_status r = HP_OK;
+  if (s->tmp && hipFree(s->tmp) != hipSuccess) r = hp::fail(HP_EDEVICE, "stencil buffer free failed");
   delete s;
-  return HP_OK;
+  return r;
 }

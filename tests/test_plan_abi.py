@@ -184,14 +184,42 @@ def test_stencil_plan_rejections():
     with pytest.raises(hp.HPError) as e:
         hp.Stencil(0, 10, 1, 0.5, 0.125)
     assert e.value.status_name == "HP_EINVAL"
+    for kw in ({"tile_rows": 48}, {"sweeps_per_launch": 9}, {"flags": 2}):
+        with pytest.raises(hp.HPError) as e:
+            hp.Stencil(10, 10, 4, 0.5, 0.125, **kw)
+        assert e.value.status_name == "HP_EINVAL", kw
     with pytest.raises(hp.HPError) as e:
-        hp.Stencil(10, 10, 9, 0.5, 0.125)
+        hp.Stencil(10, 10, 0, 0.5, 0.125)
+    assert e.value.status_name == "HP_EINVAL"
+    with pytest.raises(hp.HPError) as e:                            # more tiles than a launch holds
+        hp.Stencil(1 << 31, 1 << 20, 1, 0.5, 0.125)
     assert e.value.status_name == "HP_EUNSUPPORTED"
     s = hp.Stencil(100, 200, 4, 0.5, 0.125)
     L = hp.lib()
     assert L.hp_stencil_run(s._h, None, None, None) == 1          # null arrays
     assert L.hp_stencil_run(s._h, 4096, 4096 + 64, None) == 1     # overlapping arrays
     s.close()
+
+
+def test_stencil_plan_follows_the_workgroup_local_memory():
+    """Tile rows and sweeps per launch are checked against the W level's LDS size:
+    every choice fits it; the 32-row tile is the default (measured faster than the
+    64-row one); a plan of one launch allocates nothing (these run without a
+    device)."""
+    rows, _ = hp.level_table()
+    lds = next(r["shared_bytes"] for r in rows if r["scope"] == "W")
+
+    def tile_bytes(th, t):
+        return 2 * (th + 2 * t) * (64 + 2 * t + 1) * 4
+
+    for (r, c, steps), want in {(100, 200, 4): (32, 4), (8192, 8192, 1): (32, 1), (8192, 8192, 4): (32, 4),
+                                (8192, 8192, 8): (32, 8), (1000, 8192, 8): (32, 8)}.items():
+        with hp.Stencil(r, c, steps, 0.6, 0.1) as s:
+            i = s.info
+            assert (i["tile_rows"], i["sweeps_per_launch"], i["launches"], i["tile_cols"]) == want + (1, 64)
+            assert tile_bytes(i["tile_rows"], i["sweeps_per_launch"]) <= lds
+    with hp.Stencil(300, 300, 5, 0.6, 0.1, tile_rows=64, sweeps_per_launch=5, flags=hp.STENCIL_NO_XCD) as s:
+        assert s.info == {"tile_rows": 64, "tile_cols": 64, "sweeps_per_launch": 5, "launches": 1}
 
 
 def test_xcd_scope_planning():
