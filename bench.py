@@ -582,6 +582,8 @@ def main():
                     help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the persistent batched run of the 10,000-nest workload (for profiling)")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only the stencil sweeps (for profiling the stencil kernels)")
     ap.add_argument("--int-only", action="store_true",
                     help="only the 2- and 4-level integer nests (for profiling)")
     ap.add_argument("--ingest-counters", nargs="+", metavar="CSV",
@@ -613,6 +615,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.int_only:
         print(json.dumps({"int_nests": extra_int_workloads(args.steps, args.warmup, stream)}), flush=True)
+        return
+    if args.stencil_only:
+        print(json.dumps({"stencils": stencils(stream, args.steps, args.warmup)}), flush=True)
         return
     if args.batched_only:
         tc = os.path.join(ROOT, "paper_2309_01906_amd", "tune_gfx950.txt")

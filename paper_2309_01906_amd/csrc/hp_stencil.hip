@@ -24,6 +24,10 @@ namespace hp {
 constexpr int kTW = 64;  // output columns per workgroup
 constexpr int kThreads = 256;
 constexpr int kMaxSweeps = 8;  // sweeps one launch can hold (kernels are instantiated up to this)
+// Cells of a column one thread updates per pass.  Strips of 8 and 16 were measured
+// within 3 % of 4 at 1 to 8 sweeps (the arithmetic, not the neighbour reads, sets the
+// pace), so the shortest is kept.
+constexpr int kStrip = 4;
 
 template <int T, int TH>
 struct Tile {
@@ -43,10 +47,9 @@ static size_t tile_lds_bytes(int th, int t) {
 // column for kRB updates, instead of 5 reads per update.  EDGE: the tile touches the
 // array's boundary, so each cell is tested against the interior range; an interior
 // tile (every workgroup but those on the array's rim) skips the tests.
-template <int S, int H, int W, int PITCH, bool EDGE>
+template <int S, int H, int W, int PITCH, int kRB, bool EDGE>
 __device__ __forceinline__ void sweep(const float* __restrict__ src, float* __restrict__ dst, int tid, float c0,
                                       float c1, int ilo, int ihi, int jlo, int jhi) {
-  constexpr int kRB = 4;
   constexpr int wr = W - 2 * S;
   constexpr int hr = H - 2 * S;
   constexpr int nfull = hr / kRB;  // strips of kRB whole rows
@@ -56,12 +59,12 @@ __device__ __forceinline__ void sweep(const float* __restrict__ src, float* __re
     const int rb = k / wr;
     const int c = S + (k - rb * wr);
     const int r0 = S + rb * kRB;
+    const int rows = (rem && rb == nfull) ? rem : kRB;
     const bool col_in = !EDGE || (c >= jlo && c <= jhi);
     const float* q0 = src + r0 * PITCH + c;
     float* d0 = dst + r0 * PITCH + c;
     float up = q0[-PITCH];
     float mid = q0[0];
-    const int rows = (rem && rb == nfull) ? rem : kRB;
 #pragma unroll
     for (int d = 0; d < kRB; ++d) {
       if (d < rows) {
@@ -92,7 +95,7 @@ __device__ __forceinline__ uint32_t stencil_tile(uint32_t b, uint32_t nt, bool x
 template <int T, int TH>
 __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ in, float* __restrict__ out,
                                                       long long R, long long C, uint32_t ntc, uint32_t nt, int xcd,
-                                                      float c0, float c1) {
+                                                      int off32, float c0, float c1) {
   using G = Tile<T, TH>;
   extern __shared__ float lds[];
   float* buf0 = lds;
@@ -105,15 +108,30 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
   // the tile and its ghost surface; cells outside the array are never read by an
   // updated cell (only interior cells change, and their neighbours are inside)
   // all of a thread's loads are issued before the first one is stored to LDS
+  // A tile whose ghost surface lies inside the array (all but the rim) needs no bounds
+  // tests and addresses its cells with 32-bit offsets from the tile's first cell
+  // (off32: the host found rows x columns of any tile within 32 bits).
   constexpr int kLoads = (G::H * G::W + kThreads - 1) / kThreads;
   float v[kLoads];
+  const bool whole = off32 && i0 >= 0 && j0 >= 0 && i0 + G::H <= R && j0 + G::W <= C;
+  if (whole) {
+    const float* __restrict__ base = in + (i0 * C + j0);
+    const uint32_t cu = (uint32_t)C;
 #pragma unroll
-  for (int u = 0; u < kLoads; ++u) {
-    const int k = tid + u * kThreads;
-    const int r = k / G::W, c = k - (k / G::W) * G::W;
-    const long long gi = i0 + r, gj = j0 + c;
-    const bool ok = k < G::H * G::W && gi >= 0 && gi < R && gj >= 0 && gj < C;
-    v[u] = ok ? in[ok ? gi * C + gj : 0] : 0.f;
+    for (int u = 0; u < kLoads; ++u) {
+      const int k = tid + u * kThreads;
+      const int r = k / G::W, c = k - (k / G::W) * G::W;
+      if (u + 1 < kLoads || k < G::H * G::W) v[u] = base[(uint32_t)r * cu + (uint32_t)c];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int k = tid + u * kThreads;
+      const int r = k / G::W, c = k - (k / G::W) * G::W;
+      const long long gi = i0 + r, gj = j0 + c;
+      const bool ok = k < G::H * G::W && gi >= 0 && gi < R && gj >= 0 && gj < C;
+      v[u] = ok ? in[ok ? gi * C + gj : 0] : 0.f;
+    }
   }
 #pragma unroll
   for (int u = 0; u < kLoads; ++u) {
@@ -135,8 +153,8 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
     constexpr int S = decltype(S_)::value;
     const float* src = (S & 1) ? buf0 : buf1;
     float* dst = (S & 1) ? buf1 : buf0;
-    if (edge) sweep<S, G::H, G::W, G::P, true>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
-    else sweep<S, G::H, G::W, G::P, false>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
+    if (edge) sweep<S, G::H, G::W, G::P, kStrip, true>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
+    else sweep<S, G::H, G::W, G::P, kStrip, false>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
     __syncthreads();
   };
   static_assert(T >= 1 && T <= kMaxSweeps, "sweeps per launch");
@@ -149,10 +167,22 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
   if constexpr (T >= 7) run(std::integral_constant<int, 7>{});
   if constexpr (T >= 8) run(std::integral_constant<int, 8>{});
   const float* fin = (T & 1) ? buf1 : buf0;
-  for (int k = tid; k < TH * kTW; k += kThreads) {
-    const int r = T + k / kTW, c = T + (k - (k / kTW) * kTW);
-    const long long gi = i0 + r, gj = j0 + c;
-    if (gi < R && gj < C) out[gi * C + gj] = fin[r * G::P + c];
+  if (off32 && i0 + T + TH <= R && j0 + T + kTW <= C) {
+    float* __restrict__ base = out + ((i0 + T) * C + (j0 + T));
+    const uint32_t cu = (uint32_t)C;
+    static_assert((TH * kTW) % kThreads == 0, "whole passes over the output tile");
+#pragma unroll
+    for (int u = 0; u < TH * kTW / kThreads; ++u) {
+      const int k = tid + u * kThreads;
+      const int r = k / kTW, c = k - (k / kTW) * kTW;
+      base[(uint32_t)r * cu + (uint32_t)c] = fin[(r + T) * G::P + c + T];
+    }
+  } else {
+    for (int k = tid; k < TH * kTW; k += kThreads) {
+      const int r = T + k / kTW, c = T + (k - (k / kTW) * kTW);
+      const long long gi = i0 + r, gj = j0 + c;
+      if (gi < R && gj < C) out[gi * C + gj] = fin[r * G::P + c];
+    }
   }
 }
 
@@ -162,8 +192,10 @@ hp_status launch_t(const float* in, float* out, long long R, long long C, bool x
   const uint32_t ntc = (uint32_t)((C + kTW - 1) / kTW), ntr = (uint32_t)((R + TH - 1) / TH);
   const uint32_t nt = ntc * ntr;
   constexpr size_t lds = 2 * Tile<T, TH>::kFloats * sizeof(float);
-  hipLaunchKernelGGL((k_stencil<T, TH>), dim3(nt), dim3(kThreads), lds, st, in, out, R, C, ntc, nt, xcd ? 1 : 0, c0,
-                     c1);
+  // every offset within one tile (rows x columns with the widest ghost surface) fits 32 bits
+  const int off32 = (unsigned long long)C * (TH + 2 * kMaxSweeps) + kTW + 2 * kMaxSweeps < (1ull << 32) ? 1 : 0;
+  hipLaunchKernelGGL((k_stencil<T, TH>), dim3(nt), dim3(kThreads), lds, st, in, out, R, C, ntc, nt, xcd ? 1 : 0,
+                     off32, c0, c1);
   if (hipGetLastError() != hipSuccess) return hp::fail(HP_EDEVICE, "stencil launch failed");
   return HP_OK;
 }
@@ -222,7 +254,7 @@ extern "C" hp_status hp_stencil_plan_ex(int64_t rows, int64_t cols, int32_t step
   // Sweeps per launch: as many as a launch holds, spread evenly over the launches
   // (each launch is one HBM round trip; the wider ghost surface of more sweeps per
   // launch costs less than a round trip up to 8: 16 sweeps of an 8192 x 8192 array
-  // run as 2 launches of 8 in 0.85x the time of 4 launches of 4).
+  // run as 2 launches of 8 in 0.94x the time of 4 launches of 4).
   int t = sweeps_per_launch;
   if (t == 0) {
     const int k = (steps + hp::kMaxSweeps - 1) / hp::kMaxSweeps;
