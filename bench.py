@@ -360,8 +360,10 @@ def stencils(stream, steps=20, warmup=3):
     sweeps in one launch and 16 in two, tiled through LDS with a ghost surface, the
     tiles dealt to the XCDs in bands; 1 and 8 sweeps also without the XCD bands.
     `effective_GBps` counts one read and one write of every cell per sweep (what
-    separate sweeps would move); `hbm_GBps` counts what the launches move: each tile
-    with its ghost cells read once, the array written once."""
+    separate sweeps would move); `launch_GBps` one read and one write of every cell
+    per launch, which is what HBM carries when the ghost cells that neighbouring
+    tiles share are read once (the HBM counters show this with the XCD bands, and
+    about twice the reads without them at one sweep)."""
     import torch
 
     import paper_2309_01906_amd as hp
@@ -385,12 +387,11 @@ def stencils(stream, steps=20, warmup=3):
                 ev.append(s_.elapsed_time(e_))
             inf = st.info
         us = pct(ev, 50) * 1e3
-        th, tw, per = inf["tile_rows"], inf["tile_cols"], inf["sweeps_per_launch"]
-        amp = (th + 2 * per) * (tw + 2 * per) / (th * tw)
         key = f"sweeps_{t}" + ("_no_xcd" if flags else "")
-        res[key] = {"p50_us": round(us, 1), "tile": [th, tw], "launches": inf["launches"],
+        res[key] = {"p50_us": round(us, 1), "tile": [inf["tile_rows"], inf["tile_cols"]],
+                    "sweeps_per_launch": inf["sweeps_per_launch"], "launches": inf["launches"],
                     "effective_GBps": round(8.0 * R * C * t / us / 1e3, 1),
-                    "hbm_GBps": round(inf["launches"] * (4.0 * amp + 4.0) * R * C / us / 1e3, 1)}
+                    "launch_GBps": round(inf["launches"] * 8.0 * R * C / us / 1e3, 1)}
     del x, y
     return res
 
