@@ -393,16 +393,17 @@ hp_status hp_server_destroy(hp_server_t s);
  * `steps` five-point Jacobi sweeps of a rows x cols row-major float array,
  *   B[i][j] = c0 A[i][j] + c1 ((A[i-1][j] + A[i+1][j]) + (A[i][j-1] + A[i][j+1]))
  * for 1 <= i <= rows-2, 1 <= j <= cols-2 (fp32, in exactly this order, no fused
- * multiply-add); boundary cells keep their values.  Levels: each workgroup reads a
- * tile_rows x 64 output tile plus a ghost surface T cells wide into LDS once, runs
- * T sweeps there and writes the tile once; each lane updates column strips of 4
- * cells from registers; the tiles are dealt to the XCDs in bands, so ghost cells
+ * multiply-add); boundary cells keep their values.  Levels: each workgroup (8
+ * threads per tile row) reads a tile_rows x 64 output tile plus a ghost surface T
+ * cells wide into LDS once, runs T sweeps there and writes the tile once; each lane
+ * updates column strips of 4 cells from registers; the tiles are dealt to the XCDs in bands, so ghost cells
  * that neighbouring tiles share come from HBM once into the XCD's L2.  More sweeps
  * than one launch holds (8) run as ceil(steps / T) launches, alternating between
  * d_out and a rows x cols buffer the plan allocates, so that the last writes d_out.
- * hp_stencil_plan: rows, cols >= 1, steps >= 1 (HP_EINVAL); 32-row tiles and at
- *   most 8 sweeps per launch, spread evenly over the launches; the tile must fit
- *   the workgroup level's local memory (hp_level_table).
+ * hp_stencil_plan: rows, cols >= 1, steps >= 1 (HP_EINVAL); at most 8 sweeps per
+ *   launch, spread evenly over the launches; 64-row tiles from 6 sweeps per launch
+ *   when they fit the workgroup level's local memory and the array gives the fill
+ *   target of workgroups (both from hp_level_table), else 32-row tiles.
  * hp_stencil_plan_ex: the same with tile_rows (0: choose, 32 or 64), sweeps per
  *   launch (0: choose, 1..8) and flags (HP_STENCIL_NO_XCD: tile b on workgroup b);
  *   HP_EINVAL for other values, HP_EUNSUPPORTED when the tile does not fit LDS or

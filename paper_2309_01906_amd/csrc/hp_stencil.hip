@@ -22,7 +22,9 @@
 namespace hp {
 
 constexpr int kTW = 64;  // output columns per workgroup
-constexpr int kThreads = 256;
+// threads per workgroup: 8 per output row of the tile (256 for 32 rows, 512 for 64)
+constexpr int threads_of(int th) { return 8 * th; }
+constexpr int kMaxThreads = threads_of(64);
 constexpr int kMaxSweeps = 8;  // sweeps one launch can hold (kernels are instantiated up to this)
 // Cells of a column one thread updates per pass.  Strips of 8 and 16 were measured
 // within 3 % of 4 at 1 to 8 sweeps (the arithmetic, not the neighbour reads, sets the
@@ -47,7 +49,7 @@ static size_t tile_lds_bytes(int th, int t) {
 // column for kRB updates, instead of 5 reads per update.  EDGE: the tile touches the
 // array's boundary, so each cell is tested against the interior range; an interior
 // tile (every workgroup but those on the array's rim) skips the tests.
-template <int S, int H, int W, int PITCH, int kRB, bool EDGE>
+template <int S, int H, int W, int PITCH, int kRB, int NT, bool EDGE>
 __device__ __forceinline__ void sweep(const float* __restrict__ src, float* __restrict__ dst, int tid, float c0,
                                       float c1, int ilo, int ihi, int jlo, int jhi) {
   constexpr int wr = W - 2 * S;
@@ -55,7 +57,7 @@ __device__ __forceinline__ void sweep(const float* __restrict__ src, float* __re
   constexpr int nfull = hr / kRB;  // strips of kRB whole rows
   constexpr int rem = hr - nfull * kRB;
   constexpr int n = (nfull + (rem ? 1 : 0)) * wr;
-  for (int k = tid; k < n; k += kThreads) {
+  for (int k = tid; k < n; k += NT) {
     const int rb = k / wr;
     const int c = S + (k - rb * wr);
     const int r0 = S + rb * kRB;
@@ -93,10 +95,11 @@ __device__ __forceinline__ uint32_t stencil_tile(uint32_t b, uint32_t nt, bool x
 }
 
 template <int T, int TH>
-__global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ in, float* __restrict__ out,
+__global__ void __launch_bounds__(threads_of(TH)) k_stencil(const float* __restrict__ in, float* __restrict__ out,
                                                       long long R, long long C, uint32_t ntc, uint32_t nt, int xcd,
                                                       int off32, float c0, float c1) {
   using G = Tile<T, TH>;
+  constexpr int kThreads = threads_of(TH);
   extern __shared__ float lds[];
   float* buf0 = lds;
   float* buf1 = lds + G::kFloats;
@@ -153,8 +156,8 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const float* __restrict__ 
     constexpr int S = decltype(S_)::value;
     const float* src = (S & 1) ? buf0 : buf1;
     float* dst = (S & 1) ? buf1 : buf0;
-    if (edge) sweep<S, G::H, G::W, G::P, kStrip, true>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
-    else sweep<S, G::H, G::W, G::P, kStrip, false>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
+    if (edge) sweep<S, G::H, G::W, G::P, kStrip, kThreads, true>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
+    else sweep<S, G::H, G::W, G::P, kStrip, kThreads, false>(src, dst, tid, c0, c1, ilo, ihi, jlo, jhi);
     __syncthreads();
   };
   static_assert(T >= 1 && T <= kMaxSweeps, "sweeps per launch");
@@ -194,7 +197,7 @@ hp_status launch_t(const float* in, float* out, long long R, long long C, bool x
   constexpr size_t lds = 2 * Tile<T, TH>::kFloats * sizeof(float);
   // every offset within one tile (rows x columns with the widest ghost surface) fits 32 bits
   const int off32 = (unsigned long long)C * (TH + 2 * kMaxSweeps) + kTW + 2 * kMaxSweeps < (1ull << 32) ? 1 : 0;
-  hipLaunchKernelGGL((k_stencil<T, TH>), dim3(nt), dim3(kThreads), lds, st, in, out, R, C, ntc, nt, xcd ? 1 : 0,
+  hipLaunchKernelGGL((k_stencil<T, TH>), dim3(nt), dim3(threads_of(TH)), lds, st, in, out, R, C, ntc, nt, xcd ? 1 : 0,
                      off32, c0, c1);
   if (hipGetLastError() != hipSuccess) return hp::fail(HP_EDEVICE, "stencil launch failed");
   return HP_OK;
@@ -260,17 +263,22 @@ extern "C" hp_status hp_stencil_plan_ex(int64_t rows, int64_t cols, int32_t step
     const int k = (steps + hp::kMaxSweeps - 1) / hp::kMaxSweeps;
     t = (steps + k - 1) / k;
   }
-  // Tile rows: a 64-row tile reads 17% fewer ghost cells and recomputes fewer of
-  // them at 8 sweeps, but its buffers leave room for 3 workgroups per CU instead of 5;
-  // on an 8192 x 8192 array the 32-row tile is faster at every sweep count (1 to 8),
-  // so it is the default and the taller one is there on request.  Either must fit
-  // the workgroup's local memory.
-  const int th = tile_rows ? tile_rows : 32;
+  // Tile rows: a 64-row tile (512 threads) recomputes fewer ghost cells per output
+  // cell -- 24 % extra updates at 8 sweeps instead of 36 % -- but holds 3 workgroups
+  // per CU instead of 5.  On an 8192 x 8192 array it is 6-9 % faster from 6 sweeps
+  // per launch on and slower below, so it is taken from 6 sweeps when it fits the
+  // workgroup's local memory and the array still gives the chip its fill target of
+  // workgroups (both from the level-property table).
+  int th = tile_rows;
+  if (th == 0) {
+    const int64_t tiles64 = ((rows + 63) / 64) * ((cols + kTW - 1) / kTW);
+    th = (t >= 6 && (int64_t)hp::tile_lds_bytes(64, t) <= lds && tiles64 >= fill) ? 64 : 32;
+  }
   if ((int64_t)hp::tile_lds_bytes(th, t) > lds)
     return hp::fail(HP_EUNSUPPORTED, "a %d-row tile with %d sweeps needs %zu bytes of LDS", th, t,
                     hp::tile_lds_bytes(th, t));
   // one workgroup per tile, and a launch holds at most 2^32 - 1 work-items
-  const int64_t max_tiles = (int64_t)(0xFFFFFFFFu / (uint32_t)hp::kThreads);
+  const int64_t max_tiles = (int64_t)(0xFFFFFFFFu / (uint32_t)hp::kMaxThreads);
   if (rows > (int64_t(1) << 62) / cols || (rows + th - 1) / th > max_tiles / ((cols + kTW - 1) / kTW))
     return hp::fail(HP_EUNSUPPORTED, "array of %lld x %lld cells needs more tiles than a launch holds",
                     (long long)rows, (long long)cols);

@@ -202,18 +202,20 @@ def test_stencil_plan_rejections():
 
 
 def test_stencil_plan_follows_the_workgroup_local_memory():
-    """Tile rows and sweeps per launch are checked against the W level's LDS size:
-    every choice fits it; the 32-row tile is the default (measured faster than the
-    64-row one); a plan of one launch allocates nothing (these run without a
-    device)."""
-    rows, _ = hp.level_table()
+    """Tile rows and sweeps per launch follow the level-property table: every choice
+    fits the W level's LDS; the 64-row tile is taken from 6 sweeps per launch when the
+    array still gives the fill target of workgroups; a plan of one launch allocates
+    nothing (these run without a device)."""
+    rows, fill = hp.level_table()
+    assert fill == 2048
     lds = next(r["shared_bytes"] for r in rows if r["scope"] == "W")
 
     def tile_bytes(th, t):
         return 2 * (th + 2 * t) * (64 + 2 * t + 1) * 4
 
     for (r, c, steps), want in {(100, 200, 4): (32, 4), (8192, 8192, 1): (32, 1), (8192, 8192, 4): (32, 4),
-                                (8192, 8192, 8): (32, 8), (1000, 8192, 8): (32, 8)}.items():
+                                (8192, 8192, 5): (32, 5), (8192, 8192, 6): (64, 6), (8192, 8192, 8): (64, 8),
+                                (1024, 8192, 8): (64, 8), (900, 8192, 8): (32, 8), (100, 200, 8): (32, 8)}.items():
         with hp.Stencil(r, c, steps, 0.6, 0.1) as s:
             i = s.info
             assert (i["tile_rows"], i["sweeps_per_launch"], i["launches"], i["tile_cols"]) == want + (1, 64)
