@@ -8,7 +8,9 @@ levels mapped grid -> waves -> lanes.  A step is one hp_run over the whole array
 
 Prints ONE JSON line (rank 0, N = 1).  Only one GPU is used; --gpus > 1 exits.
 The CPU baseline leg times the oracle (test infrastructure) on the host cores and
-states the error of the GPU result against it.
+states the error of the GPU results against it: the headline's, the ragged nest's,
+the batch's and the served requests'.  Those checks read results the timed GPU runs
+left behind; with --no-cpu-baseline nothing calls the oracle.
 """
 from __future__ import annotations
 
@@ -26,6 +28,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "achieved HBM GB/s (% of peak) for nested reduction; batched-vs-plain; p50/p99"
+# the CPU baseline leg: the oracle checks of GPU results (off with --no-cpu-baseline)
+ORACLE_CHECKS = True
 PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 KERNEL_SOURCES = ["hp_nest.h", "hp_lanes.h", "hp_nest_f32.hip", "hp_internal.h", "hp_plan.cpp"]
 
@@ -281,7 +285,6 @@ def extra_ragged_and_xcd(steps, warmup, stream):
     (HP_FLAG_NO_XCD) and with an explicit X level."""
     import torch
 
-    import oracle
     import paper_2309_01906_amd as hp
     import workloads
     res = {}
@@ -294,13 +297,15 @@ def extra_ragged_and_xcd(steps, warmup, stream):
         wall, ev = time_plan(p, d, out, steps, warmup, stream)
         nb = x.nbytes + p.info["out_bytes"]
         got = out.cpu().numpy()
-        ref = oracle.reduce(x, ext, (0, 1), oracle.F32, threads=16)
-        sa = oracle.abs_sum(x, ext, (0, 1), oracle.F32, threads=16)
-        ok, plain, scaled = oracle.within_tolerance(got, ref, sa, 1e-6)
         res["ragged_fp32_4096x65537"] = {
             "bytes": nb, "kernel": p.info["kernel_name"], "flat_block": p.info["flat_block"],
-            "p50_us": round(pct(ev, 50) * 1e3, 1), "GBps": round(nb / (pct(ev, 50) * 1e-3) / 1e9, 1),
-            "all_outputs_within_1e-6": bool(ok), "max_rel_err": plain}
+            "p50_us": round(pct(ev, 50) * 1e3, 1), "GBps": round(nb / (pct(ev, 50) * 1e-3) / 1e9, 1)}
+        if ORACLE_CHECKS:
+            import oracle
+            ref = oracle.reduce(x, ext, (0, 1), oracle.F32, threads=16)
+            sa = oracle.abs_sum(x, ext, (0, 1), oracle.F32, threads=16)
+            ok, plain, scaled = oracle.within_tolerance(got, ref, sa, 1e-6)
+            res["ragged_fp32_4096x65537"].update({"all_outputs_within_1e-6": bool(ok), "max_rel_err": plain})
     del d, x
     xcd = {}
     c3 = workloads.C3
@@ -440,7 +445,7 @@ def batched_vs_plain(stream, steps=20, warmup=3, plain=True, verify=True):
     got_b = out_a.cpu().numpy()
     nbytes = st["bytes"]
     err = None
-    if verify:
+    if verify and ORACLE_CHECKS:
         import oracle
         cases = [(host[bw.offsets[i]:bw.offsets[i] + n.elems].reshape(n.extents), n.extents, n.ops, oracle.BF16,
                   got_b[oo[i]:oo[i + 1]]) for i, n in enumerate(bw.nests)]
@@ -524,7 +529,7 @@ def serve_stream(pools, duration_s, rate, warmup_s, verify):
         "p999_us": round(float(np.percentile(ls, 99.9)), 1), "max_us": round(float(ls.max()), 1),
         "GBps": round(nb / (t_last - t_first) / 1e3, 2),
     }
-    if verify:
+    if verify and ORACLE_CHECKS:
         import oracle
         got = out.cpu().numpy()
         cases = []
@@ -536,6 +541,7 @@ def serve_stream(pools, duration_s, rate, warmup_s, verify):
             g = g.view(np.int64) if kind == hp.I64 else g.view(np.int32)[:g.size].copy() if kind == hp.I32 else g
             cases.append((x, r.nest.extents, r.nest.ops, r.nest.dtype, g))
         res["error_vs_fp64_oracle"] = error_statement(oracle.verify(cases))
+    if verify:
         # start-up: p99 per 100 ms of arrival time over the first two seconds
         res["startup_p99_us_per_100ms"] = [round(float(np.percentile(lat[(arr >= a) & (arr < a + 1e5)], 99)), 1)
                                            for a in np.arange(0, 2e6, 1e5) if np.any((arr >= a) & (arr < a + 1e5))]
@@ -613,6 +619,8 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    global ORACLE_CHECKS
+    ORACLE_CHECKS = not args.no_cpu_baseline
     stream = torch.cuda.current_stream()
     if args.int_only:
         print(json.dumps({"int_nests": extra_int_workloads(args.steps, args.warmup, stream)}), flush=True)
