@@ -147,15 +147,38 @@ bool simple_desc_of(const DevPlan& P, SimpleDesc* D) {
   return true;
 }
 
-void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B) {
+void deal_tasks(const int2* ordered, const double* weight, int n, int grid, int2* out, BatchArgs* B) {
   const int nq = grid < kQueues ? (grid < 1 ? 1 : grid) : kQueues;
-  int pos = 0;
+  // queue q is served by the workgroups b < grid with b % kQueues == q; a task goes
+  // to the queue whose cost per serving workgroup would be least with it (ties: the
+  // lowest queue)
+  double load[kQueues] = {};
+  int cnt[kQueues] = {};
+  double groups[kQueues] = {};
+  for (int q = 0; q < nq; ++q) groups[q] = (double)((grid - q + kQueues - 1) / kQueues);
+  std::vector<int> qof((size_t)n);
+  for (int j = 0; j < n; ++j) {
+    int best = 0;
+    double best_v = (load[0] + weight[j]) / groups[0];
+    for (int q = 1; q < nq; ++q) {
+      const double v = (load[q] + weight[j]) / groups[q];
+      if (v < best_v) {
+        best_v = v;
+        best = q;
+      }
+    }
+    qof[(size_t)j] = best;
+    load[best] += weight[j];
+    ++cnt[best];
+  }
+  int pos = 0, fill[kQueues];
   for (int q = 0; q < kQueues; ++q) {
     B->qbeg[q] = pos;
-    if (q < nq)
-      for (int j = q; j < n; j += nq) out[pos++] = ordered[j];
+    fill[q] = pos;
+    pos += cnt[q];
   }
   B->qbeg[kQueues] = pos;
+  for (int j = 0; j < n; ++j) out[fill[qof[(size_t)j]]++] = ordered[j];
   // several tasks per atomic when every worker has many to do
   const long long workers = (long long)grid * kBatchGroupWaves;
   long long k = (long long)n / (workers * 8);
@@ -370,10 +393,15 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
       return wa > wc;
     });
     std::vector<int2> ordered((size_t)ntask[g]);
+    std::vector<double> weight((size_t)ntask[g]);
     long long k = 0;
-    for (int64_t i : mem)
-      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w)
+    for (int64_t i : mem) {
+      const double wt = task_cost((double)b->infos[(size_t)i].in_bytes / (double)b->plans[(size_t)i].grid);
+      for (long long w = 0; w < b->plans[(size_t)i].grid; ++w) {
+        weight[(size_t)k] = wt;
         ordered[(size_t)k++] = make_int2((int)i, (int)w | (b->is_simple[(size_t)i] ? kSimpleTask : 0));
+      }
+    }
     Group G;
     G.family = keys[g].first;
     G.chunk = keys[g].second;
@@ -389,8 +417,8 @@ hp_status hp::batch_from_plans(const std::vector<Lowered>& plans, uint32_t flags
     const long long need = (G.n_tasks + kBatchGroupWaves - 1) / kBatchGroupWaves;
     if (grid > need) grid = need;
     G.grid = (int)grid;
-    deal_tasks(ordered.data(), (int)ntask[g], G.grid, reinterpret_cast<int2*>(host_arena.data() + task_off[g]),
-               &G.args);
+    deal_tasks(ordered.data(), weight.data(), (int)ntask[g], G.grid,
+               reinterpret_cast<int2*>(host_arena.data() + task_off[g]), &G.args);
     G.args.tasks = reinterpret_cast<const int2*>((unsigned char*)b->arena + task_off[g]);
     G.args.simple = b->d_simple;
     G.args.ctr = reinterpret_cast<unsigned int*>((unsigned char*)b->arena + ctr_off[g]);

@@ -7,7 +7,8 @@ namespace hp {
 
 // Persistent batched kernels: workers pop (nest, workgroup) tasks with atomic
 // counters -- a dynamic schedule on the grid level.  The tasks are dealt, largest
-// first, into kQueues queues with one counter each; workgroup b takes from queue
+// first, each to the queue with the least estimated work so far, into kQueues
+// queues with one counter each; workgroup b takes from queue
 // b % kQueues, which sits on one XCD (workgroups are dealt round-robin to the 8
 // XCDs).  Atomics on one address are serialised in the L2 (some 20 ns apiece), so
 // a batch of tens of thousands of small tasks needs many counters: 64 queues, 8
@@ -222,10 +223,16 @@ hp_status launch_batch(int family, int chunk, const BatchArgs& B, int grid, int 
 hp_status warm_batch_kernels(hipStream_t st);
 // Clear n counters (a kernel, so that it can sit in a captured graph).
 hp_status launch_clear(unsigned int* ctr, int n, hipStream_t st);
-// Deal n tasks, given largest first, round-robin into the queues that a grid of
-// `grid` workgroups serves; writes them queue by queue to `out` and fills B->qbeg
-// and B->per_pop.
-void deal_tasks(const int2* ordered, int n, int grid, int2* out, BatchArgs* B);
+// Deal n tasks, given largest first with their estimated costs (weight[j], e.g.
+// input bytes plus a per-task overhead), into the queues that a grid of `grid`
+// workgroups serves: each task goes to the queue with the least cost so far
+// (longest-processing-time-first), so the queues end together; a queue keeps its
+// tasks largest first.  Writes them queue by queue to `out` and fills B->qbeg and
+// B->per_pop.
+void deal_tasks(const int2* ordered, const double* weight, int n, int grid, int2* out, BatchArgs* B);
+// estimated cost of one task of `bytes` input bytes, in bytes: the data plus the
+// fixed latency of starting a task (descriptor, first loads, combine, write)
+inline double task_cost(double bytes) { return bytes + 4096.0; }
 // Counter words one batch launch uses (cleared before each launch).
 constexpr int kCtrWords = kQueues * kCtrStride;
 // Resident workgroups per CU for that kernel.

@@ -254,9 +254,15 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs, boo
       return wa > wc;
     });
     std::vector<int2> ordered((size_t)Lo.ntask[g]);
+    std::vector<double> weight((size_t)Lo.ntask[g]);
     long long k = 0;
-    for (int64_t i : mem)
-      for (long long w = 0; w < rs[(size_t)i]->L.dp.grid; ++w) ordered[(size_t)k++] = make_int2((int)i, (int)w);
+    for (int64_t i : mem) {
+      const double wt = task_cost((double)rs[(size_t)i]->L.info.in_bytes / (double)rs[(size_t)i]->L.dp.grid);
+      for (long long w = 0; w < rs[(size_t)i]->L.dp.grid; ++w) {
+        weight[(size_t)k] = wt;
+        ordered[(size_t)k++] = make_int2((int)i, (int)w);
+      }
+    }
     const int key = occ_key(Lo.keys[g].first, Lo.keys[g].second);
     auto it = S->occ.find(key);
     int o;
@@ -271,7 +277,8 @@ hp_status launch_slot(hp_server_s* S, Slot& slot, std::vector<Request*>& rs, boo
     const long long need = (Lo.ntask[g] + kBatchGroupWaves - 1) / kBatchGroupWaves;
     if (gr > need) gr = need;
     grid[g] = (int)gr;
-    deal_tasks(ordered.data(), (int)Lo.ntask[g], grid[g], reinterpret_cast<int2*>(h + Lo.task_off[g]), &args[g]);
+    deal_tasks(ordered.data(), weight.data(), (int)Lo.ntask[g], grid[g], reinterpret_cast<int2*>(h + Lo.task_off[g]),
+               &args[g]);
     memset(h + Lo.ctr_off[g], 0, kCtrWords * sizeof(unsigned int));
   }
   if (!Lo.folds.empty()) memcpy(h + Lo.fold_off, Lo.folds.data(), Lo.folds.size() * sizeof(FoldTask));
