@@ -589,6 +589,8 @@ def main():
                     help="also run one 1 GiB device copy (for scaling rocprofv3 byte counters)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the persistent batched run of the 10,000-nest workload (for profiling)")
+    ap.add_argument("--ordered-only", action="store_true",
+                    help="only the ordered products (for profiling the ordered kernels)")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only the stencil sweeps (for profiling the stencil kernels)")
     ap.add_argument("--int-only", action="store_true",
@@ -624,6 +626,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.int_only:
         print(json.dumps({"int_nests": extra_int_workloads(args.steps, args.warmup, stream)}), flush=True)
+        return
+    if args.ordered_only:
+        print(json.dumps({"ordered_products": ordered_products(stream, args.steps, args.warmup)}), flush=True)
         return
     if args.stencil_only:
         print(json.dumps({"stencils": stencils(stream, args.steps, args.warmup)}), flush=True)

@@ -142,7 +142,7 @@ def kernel_name(inf: PlanInfo, ops=None) -> str:
     kernel's first template argument is the innermost operator (from ``ops``)."""
     c = inf.chunk
     if inf.kernel == KERNEL_ORDERED:
-        return "hp::k_ordered<2, 8>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 8>"
+        return "hp::k_ordered<2, 8>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 4>"
     if inf.kernel == KERNEL_INT_CHAIN:
         return f"hp::k_nest_i32_chain<{OP_TEMPLATE[_op(ops[-1])] if ops else '?'}, {inf.nseg}>"
     if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP):

@@ -2,11 +2,11 @@
 // 2x2 matrices modulo 2^64 (HP_OP_PROD).  The paper points out that OpenMP
 // reductions must be commutative (section 2); here siblings are combined strictly
 // in iteration order at every level of the hierarchy:
-//   lane    K consecutive elements (read from LDS after a coalesced load of the
-//           tile) multiplied in registers, a balanced tree over adjacent pairs;
+//   lane    one contiguous 64th of a chunk, read K elements (one 128-byte line) at
+//           a time through LDS after coalesced loads, each K as a balanced tree
+//           over adjacent pairs, appended to the lane's running product;
 //   wave    a xor butterfly in which the lower-lane half always stands on the left,
-//           so after log2(64) steps every lane holds the tile's product in order;
-//   chunk   tile products appended left to right by the wave;
+//           so after log2(64) steps every lane holds the chunk's product in order;
 //   grid    chunk products folded left to right by a second kernel.
 // The reduced block of one output is contiguous (row-major input), so every level
 // of a nested product collapses into one ordered product over the block.
@@ -90,14 +90,32 @@ struct Slice {
   __device__ static __forceinline__ int word_slot(int wi) { return (wi / RW) * kRowBytes + (wi % RW) * 16; }
 };
 
-// Every wave is a worker: unit u = (output u / C, chunk u % C), grid-stride.  A
-// tile is read from HBM with coalesced 16-byte loads (word q*64 + lane), staged in
-// the wave's LDS slice, and read back as one contiguous run of K elements per
-// lane.  The next tile's loads are issued before the current tile is multiplied.
+// Order-keeping butterfly step on lane bit b: the half with the lower lanes stays
+// on the left, so after the steps on bits 0..5 every lane holds the product of the
+// 64 lanes' values in lane order.
+template <int W>
+__device__ __forceinline__ Elem<W> ordered_step(const Elem<W>& run, int b, int lane) {
+  const Elem<W> other = shfl<W>(run, 1 << b, lane);
+  const bool low = ((lane >> b) & 1) == 0;
+  return mul<W>(pick<W>(low, run, other), pick<W>(low, other, run));
+}
+
+// Every wave is a worker: unit u = (output u / C, chunk u % C), grid-stride.  The
+// unit's range is cut into 64 contiguous parts, lane l taking part l, so a lane's
+// product is a plain running product and the lanes meet only once, in the
+// order-keeping butterfly after the last tile.  A tile is every lane's next K
+// elements (one 128-byte line per lane): read from HBM with coalesced 16-byte loads
+// (load row q, lane l: word l % R of lane 64/R q + l / R's line, R words per line),
+// staged in the wave's LDS slice, and read back as each lane's own K elements; the
+// next tile's loads are issued before the current tile is multiplied.  The K
+// elements are multiplied as a balanced tree and appended to the lane's product:
+// K multiplies per K elements.
 template <int W, int K>
 __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd, const u64* __restrict__ in,
                                                  u64* __restrict__ out, u64* __restrict__ ws) {
   constexpr int kRunWords = K * W / 2;  // sixteen-byte words per lane run
+  static_assert(kRunWords * 16 == 128, "a lane run is one 128-byte line");
+  constexpr int kJ = 64 / kRunWords;  // lane runs per load row
   using SL = Slice<kRunWords>;
   constexpr int kRowBytes = SL::kRowBytes;
   constexpr int kWaveSlice = SL::kBytes;
@@ -110,28 +128,35 @@ __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd,
   const long long C = P.gsplit, B = P.ord_block, S = P.ord_span;
   const long long units = P.n_out * C;
   const long long nwv = (long long)gridDim.x * (blockDim.x >> 6);
-  constexpr long long kTile = 64LL * K;
   constexpr int kEw = W / 2;  // sixteen-byte words per element
   // identity words: affine (1, 0); matrix rows (1, 0) and (0, 1)
   auto unit_word = [](int h) -> u64x2 { return h == 0 ? u64x2{1ull, 0ull} : u64x2{0ull, 1ull}; };
+  // in load row q this lane fetches word lane % R of the line of lane kJ q + lane / R
+  const int lw = lane % kRunWords, lh = lw % kEw;
   for (long long u = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < units; u += nwv) {
     const long long o = u / C, c = u - o * C;
     const u64* blk = in + (size_t)o * B * W;
     const long long lo = c * S, hi = (lo + S < B) ? lo + S : B;
+    // elements per lane: whole tiles; the last lanes' parts may be short or empty
+    const long long part = ((hi - lo + 63) / 64 + K - 1) / K * K;
+    const long long le0 = lo + (long long)(lane / kRunWords) * part + lw / kEw;
+    const u64* l0 = blk + (size_t)lo * W + lh * 2;  // an address inside the unit, for masked words
     auto fetch = [&](long long t, u64x2* g) {
+      const long long lt = le0 + t;
+      const u64* lp = blk + (size_t)lt * W + lh * 2;
 #pragma unroll
       for (int q = 0; q < kRunWords; ++q) {
-        const int wi = q * 64 + lane;
-        const long long e = t + wi / kEw;
-        const bool ok = e < hi;
-        g[q] = __builtin_nontemporal_load((G2*)(blk + (size_t)(ok ? e : lo) * W + (wi % kEw) * 2));
-        if (!ok) g[q] = unit_word(wi % kEw);
+        const long long qo = (long long)(q * kJ) * part;  // lanes kJ q + ...: q kJ parts further
+        const bool ok = lt < hi - qo;
+        g[q] = __builtin_nontemporal_load((G2*)(ok ? lp + (size_t)qo * W : l0));
+        if (!ok) g[q] = unit_word(lh);
       }
     };
     u64x2 g[kRunWords];
-    fetch(lo, g);
+    fetch(0, g);
     Elem<W> acc = unit<W>();
-    for (long long t = lo; t < hi; t += kTile) {
+#pragma unroll 1
+    for (long long t = 0; t < part; t += K) {
 #pragma unroll
       for (int q = 0; q < kRunWords; ++q) *reinterpret_cast<u64x2*>(slice + SL::word_slot(q * 64 + lane)) = g[q];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -148,7 +173,7 @@ __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd,
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __builtin_amdgcn_wave_barrier();
-      if (t + kTile < hi) fetch(t + kTile, g);  // in flight while this tile is multiplied
+      if (t + K < part) fetch(t + K, g);  // in flight while this tile is multiplied
       // the lane's K elements as a balanced tree (adjacent pairs, order kept), so
       // the multiplies of one level are independent of each other
 #pragma unroll
@@ -156,16 +181,10 @@ __global__ void __launch_bounds__(256) k_ordered(const DevPlan* __restrict__ Pd,
 #pragma unroll
         for (int j = 0; j + h < K; j += 2 * h) x[j] = mul<W>(x[j], x[j + h]);
       }
-      Elem<W> run = x[0];
-      // order-keeping butterfly: the half with the lower lanes stays on the left
-#pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        const Elem<W> other = shfl<W>(run, 1 << b, lane);
-        const bool low = ((lane >> b) & 1) == 0;
-        run = mul<W>(pick<W>(low, run, other), pick<W>(low, other, run));
-      }
-      acc = mul<W>(acc, run);
+      acc = mul<W>(acc, x[0]);
     }
+#pragma unroll
+    for (int b = 0; b < 6; ++b) acc = ordered_step<W>(acc, b, lane);
     if (lane == 0) {
       u64* dst = C > 1 ? ws + (size_t)u * W : out + (size_t)o * W;
 #pragma unroll
@@ -248,13 +267,10 @@ hp_status launch_ordered(const DevPlan& P, const DevPlan* dP, const void* in, vo
     else hipLaunchKernelGGL(k_ordered_copy<4>, dim3((unsigned)g), dim3(256), 0, st, dP, x, y);
   } else {
     const dim3 grid((unsigned)P.grid), block((unsigned)(P.nw * kWave));
-    if (aff) {
-      const size_t lds = (size_t)P.nw * Slice<8>::kBytes;
-      hipLaunchKernelGGL((k_ordered<2, 8>), grid, block, lds, st, dP, x, y, w);
-    } else {
-      const size_t lds = (size_t)P.nw * Slice<16>::kBytes;
-      hipLaunchKernelGGL((k_ordered<4, 8>), grid, block, lds, st, dP, x, y, w);
-    }
+    // a lane run of K elements is one 128-byte line: 8 affine maps or 4 matrices
+    const size_t lds = (size_t)P.nw * Slice<8>::kBytes;
+    if (aff) hipLaunchKernelGGL((k_ordered<2, 8>), grid, block, lds, st, dP, x, y, w);
+    else hipLaunchKernelGGL((k_ordered<4, 4>), grid, block, lds, st, dP, x, y, w);
     if (P.gsplit > 64) {  // long folds: a wave per output
       long long g = (P.n_out + 3) / 4;
       if (g > 4096) g = 4096;

@@ -211,10 +211,10 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
 
 // Ordered products (HP_OP_PROD over AFFINE64 / MAT2X2_64 elements).  The reduced
 // block of an output is contiguous; it is cut into gsplit chunks of ord_span
-// elements, one wavefront each.  A wave walks its chunk in tiles of 64 K elements:
-// lane l multiplies its K consecutive elements, an order-keeping butterfly
-// multiplies the 64 lane products, and the tile product is appended to the
-// chunk's product.  Chunks are folded in order by a second kernel.
+// elements, one wavefront each.  Lane l of the wave takes the l-th 64th of the
+// chunk, K elements (one 128-byte line) at a time, into a running product; an
+// order-keeping butterfly multiplies the 64 lane products once per chunk.  Chunks
+// are folded in order by a second kernel.
 static constexpr int kOrdWaves = 4;  // waves per workgroup (independent workers)
 
 static hp_status lower_ordered(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lowered* out,
@@ -237,7 +237,7 @@ static hp_status lower_ordered(const hp_nest* n, const hp_level_map* map_in, uin
     total *= e;
   }
   const int es = n->dtype == HP_AFFINE64 ? 16 : 32;
-  const int K = 8;  // elements per lane run: 128 (affine) or 256 (matrices) bytes per lane per tile
+  const int K = 128 / es;  // elements per lane run: one 128-byte line (8 affine maps, 4 matrices)
   DevPlan dp;
   memset(&dp, 0, sizeof dp);
   dp.depth = d;
