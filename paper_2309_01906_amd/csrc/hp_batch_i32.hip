@@ -1,26 +1,27 @@
-// Persistent batched kernels: int32 nests with up to three segments, depth <= 4.
+// Persistent batched kernels: int32 nests with up to three segments, depth <= 4, whose
+// ARG levels see 32-bit values (one 64-bit key per lane, as the single-nest kernels).
 #include "hp_batch_dev.h"
 
 namespace hp {
 
 __global__ void __launch_bounds__(256) k_batch_i32_0(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<IntT, 4, 1, 4, 4>(B, lds);
+  batch_run_waves<IntK, 4, 1, 4, 4>(B, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_i32_1(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<IntT, 1, 1, 4, 4>(B, lds);
+  batch_run_waves<IntK, 1, 1, 4, 4>(B, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_i32_2(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<IntT, 4, 3, 4, 4>(B, lds);
+  batch_run_waves<IntK, 4, 3, 4, 4>(B, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_i32_3(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<IntT, 1, 3, 4, 4>(B, lds);
+  batch_run_waves<IntK, 1, 3, 4, 4>(B, lds);
 }
 
 static hp_status launch_check() {

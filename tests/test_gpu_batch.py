@@ -123,6 +123,33 @@ def test_batch_mixed_families():
                 assert_match(outs[i].cpu().numpy(), np.ascontiguousarray(x), ext, ops, what=f"run {r} mixed nest {i}")
 
 
+def test_batch_arg_over_wide_sums():
+    """An ARG level over int64 sums of full-range int32 values cannot take the 64-bit
+    key carriers of the flat and segmented families: the plan names the general
+    kernel and the batch runs it in the deep family.  Mixed with narrow nests of the
+    same depth, every output matches the oracle bit for bit and one launch per nest."""
+    import paper_2309_01906_amd as hp
+    wide = [((6, 16, 64), ("NONE", "ARGMAX", "SUM"), 0), ((5, 7, 33), ("NONE", "ARGMIN", "SUM"), 0),
+            ((3, 4, 8, 64), ("NONE", "SUM", "ARGMAX", "SUM"), 0)]
+    narrow = [((6, 16, 64), ("NONE", "ARGMAX", "MAX"), 0), ((5, 7, 33), ("NONE", "SUM", "ARGMIN"), 0)]
+    for ext, ops, _ in wide:
+        assert hp.inspect(ext, ops, hp.I32)["kernel"] == hp.KERNEL_INT_DEEP, (ext, ops)
+    for ext, ops, _ in narrow:
+        assert hp.inspect(ext, ops, hp.I32)["kernel"] != hp.KERNEL_INT_DEEP, (ext, ops)
+    nests = wide + narrow
+    offs, off = [], 0
+    for ext, _, _ in nests:
+        offs.append(off)
+        off += (int(np.prod(ext)) + 7) // 8 * 8
+    host = workloads.uniform_i32(97, (off,), -(1 << 31), (1 << 31) - 1)
+    say("case batch wide sums", len(nests))
+    results, each, _ = run_batch(nests, host, offs)
+    for i, (ext, ops, _) in enumerate(nests):
+        n = int(np.prod(ext))
+        np.testing.assert_array_equal(results[0][i], each[i], err_msg=f"nest {i}")
+        assert_match(results[0][i], host[offs[i]:offs[i] + n].reshape(ext), ext, ops, what=f"wide nest {i}")
+
+
 def test_batch_mixed_families_graph_replays():
     """The multi-launch batch replayed from a graph, with and without grid-split
     nests (the fold kernel, when there is one, clears the task counters for the
