@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <new>
 #include <string>
@@ -150,26 +151,25 @@ bool simple_desc_of(const DevPlan& P, SimpleDesc* D) {
 void deal_tasks(const int2* ordered, const double* weight, int n, int grid, int2* out, BatchArgs* B) {
   const int nq = grid < kQueues ? (grid < 1 ? 1 : grid) : kQueues;
   // queue q is served by the workgroups b < grid with b % kQueues == q; a task goes
-  // to the queue whose cost per serving workgroup would be least with it (ties: the
-  // lowest queue)
+  // to the queue with the least cost per serving workgroup so far (ties: the lowest
+  // queue), found with a min-heap
   double load[kQueues] = {};
   int cnt[kQueues] = {};
   double groups[kQueues] = {};
   for (int q = 0; q < nq; ++q) groups[q] = (double)((grid - q + kQueues - 1) / kQueues);
+  typedef std::pair<double, int> Key;
+  std::vector<Key> heap;
+  heap.reserve((size_t)nq);
+  for (int q = 0; q < nq; ++q) heap.push_back(Key(0.0, q));
   std::vector<int> qof((size_t)n);
   for (int j = 0; j < n; ++j) {
-    int best = 0;
-    double best_v = (load[0] + weight[j]) / groups[0];
-    for (int q = 1; q < nq; ++q) {
-      const double v = (load[q] + weight[j]) / groups[q];
-      if (v < best_v) {
-        best_v = v;
-        best = q;
-      }
-    }
-    qof[(size_t)j] = best;
-    load[best] += weight[j];
-    ++cnt[best];
+    std::pop_heap(heap.begin(), heap.end(), std::greater<Key>());
+    const int q = heap.back().second;
+    qof[(size_t)j] = q;
+    load[q] += weight[j];
+    ++cnt[q];
+    heap.back() = Key(load[q] / groups[q], q);
+    std::push_heap(heap.begin(), heap.end(), std::greater<Key>());
   }
   int pos = 0, fill[kQueues];
   for (int q = 0; q < kQueues; ++q) {

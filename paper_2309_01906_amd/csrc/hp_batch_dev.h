@@ -208,14 +208,11 @@ __device__ __forceinline__ void batch_run_waves(const BatchArgs& B, char* lds) {
 enum Family : int32_t {
   FAM_F32_4 = 0, FAM_F32_8, FAM_BF16_4, FAM_BF16_8, FAM_I32_FLAT, FAM_I32_SEG, FAM_I32_DEEP, FAM_COUNT
 };
-// Integer nests follow the planner's kernel choice: the flat and segmented families
-// carry 64-bit keys, so a nest with an ARG level over int64 sums (planned for the
-// general kernel) runs in the deep family with (value, index) pairs.
 __host__ __device__ inline int family_of(const DevPlan& P) {
   if (P.dtype == HP_F32) return P.depth <= 4 ? FAM_F32_4 : FAM_F32_8;
   if (P.dtype == HP_BF16) return P.depth <= 4 ? FAM_BF16_4 : FAM_BF16_8;
-  if (P.kernel == HP_KERNEL_INT_FLAT) return FAM_I32_FLAT;
-  if (P.kernel == HP_KERNEL_INT_SEG || P.kernel == HP_KERNEL_INT_CHAIN) return FAM_I32_SEG;
+  if (P.depth <= 4 && P.nseg <= 1) return FAM_I32_FLAT;
+  if (P.depth <= 4 && P.nseg <= 3) return FAM_I32_SEG;
   return FAM_I32_DEEP;
 }
 

@@ -1,5 +1,7 @@
-// Persistent batched kernels: int32 nests with up to three segments, depth <= 4, whose
-// ARG levels see 32-bit values (one 64-bit key per lane, as the single-nest kernels).
+// Persistent batched kernels: int32 nests with up to three segments, depth <= 4.  One
+// segment: one 64-bit key per lane (as the single-nest kernels; an ARG level then sees
+// 32-bit input values).  Two or three: (value, index) pairs, so that an ARG level over
+// int64 sums runs in the same launch as the other served nests of its depth.
 #include "hp_batch_dev.h"
 
 namespace hp {
@@ -16,12 +18,12 @@ __global__ void __launch_bounds__(256) k_batch_i32_1(const BatchArgs B) {
 
 __global__ void __launch_bounds__(256) k_batch_i32_2(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<IntK, 4, 3, 4, 4>(B, lds);
+  batch_run_waves<IntT, 4, 3, 4, 4>(B, lds);
 }
 
 __global__ void __launch_bounds__(256) k_batch_i32_3(const BatchArgs B) {
   extern __shared__ __align__(16) char lds[];
-  batch_run_waves<IntK, 1, 3, 4, 4>(B, lds);
+  batch_run_waves<IntT, 1, 3, 4, 4>(B, lds);
 }
 
 static hp_status launch_check() {

@@ -124,9 +124,9 @@ def test_batch_mixed_families():
 
 
 def test_batch_arg_over_wide_sums():
-    """An ARG level over int64 sums of full-range int32 values cannot take the 64-bit
-    key carriers of the flat and segmented families: the plan names the general
-    kernel and the batch runs it in the deep family.  Mixed with narrow nests of the
+    """An ARG level over int64 sums of full-range int32 values cannot take 64-bit key
+    carriers: the single-nest plan names the general kernel, and in a batch the
+    segmented family carries (value, index) pairs.  Mixed with narrow nests of the
     same depth, every output matches the oracle bit for bit and one launch per nest."""
     import paper_2309_01906_amd as hp
     wide = [((6, 16, 64), ("NONE", "ARGMAX", "SUM"), 0), ((5, 7, 33), ("NONE", "ARGMIN", "SUM"), 0),
