@@ -232,11 +232,12 @@ hp_status hp_reduce_static(const hp_nest* nest, const hp_level_map* map, uint32_
  * Nests are planned as one-wavefront plans, and every wavefront of the persistent
  * workgroups is an independent worker: it starts on tasks dealt to it statically
  * and then takes (nest, workgroup) tasks from an atomic counter -- a dynamic
- * schedule on the grid level (section 3.5).  Tasks go largest first into 64 queues,
- * 8 per XCD.  Grid-split nests are folded by a second kernel after the
- * persistent one, which also resets the task counters for the next run.  Every nest keeps the plan it would get alone (its own shape and
- * the tuner cache decide it, never the batch), so its result is the same bits as
- * a single run of that plan.  Ordered products (HP_OP_PROD) are not batched.
+ * schedule on the grid level (section 3.5).  Tasks go largest first, each to the
+ * least-loaded of 64 queues, 8 per XCD.  Grid-split nests are folded by a second
+ * kernel after the persistent one, which also resets the task counters for the
+ * next run.  Every nest keeps the plan it would get alone (its own shape and the
+ * tuner cache decide it, never the batch), so its result is the same bits as a
+ * single run of that plan.  Ordered products (HP_OP_PROD) are not batched.
  */
 typedef struct hp_batch_s* hp_batch_t;
 
