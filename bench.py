@@ -405,7 +405,9 @@ def stencils(stream, steps=20, warmup=3):
 def batched_vs_plain(stream, steps=20, warmup=3, plain=True, verify=True):
     """10,000 uneven bf16 nests: one persistent launch replayed from a hipGraph vs one
     launch per nest (eager, and all launches captured in one graph).  Same plans, so
-    the outputs are compared bit for bit."""
+    the outputs are compared bit for bit.  Latency: each run timed alone (p50/p99).
+    Throughput: `back_to_back_*`, 50 runs enqueued back to back between two events;
+    the same persistent launches also without the graph (`batched_direct`)."""
     import numpy as np
     import torch
 
@@ -441,9 +443,27 @@ def batched_vs_plain(stream, steps=20, warmup=3, plain=True, verify=True):
             ev.append(s_.elapsed_time(e_))
         return (time.perf_counter() - t0) / k * 1e3, ev
 
+    def back_to_back(fn, k=50):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record(stream)
+        for _ in range(k):
+            fn()
+        e_.record(stream)
+        e_.synchronize()
+        return s_.elapsed_time(e_) / k
+
     b.set_io_ptrs(ins, [base_a + 8 * int(o) for o in oo[:-1]])
     wall_b, ev_b = timed(lambda: b.run(stream), steps, warmup)
+    b2b_g = back_to_back(lambda: b.run(stream))
     got_b = out_a.cpu().numpy()
+    with hp.Batch(nests) as bd:  # the same plans and launches, without the graph
+        bd.set_io_ptrs(ins, [base_a + 8 * int(o) for o in oo[:-1]])
+        _, ev_d = timed(lambda: bd.run(stream), steps, warmup)
+        b2b_d = back_to_back(lambda: bd.run(stream))
+        same_direct = bool(np.array_equal(out_a.cpu().numpy(), got_b))
     nbytes = st["bytes"]
     err = None
     if verify and ORACLE_CHECKS:
@@ -451,12 +471,16 @@ def batched_vs_plain(stream, steps=20, warmup=3, plain=True, verify=True):
         cases = [(host[bw.offsets[i]:bw.offsets[i] + n.elems].reshape(n.extents), n.extents, n.ops, oracle.BF16,
                   got_b[oo[i]:oo[i + 1]]) for i, n in enumerate(bw.nests)]
         err = error_statement(oracle.verify(cases))
+    def form(ev, b2b_ms):
+        return {"p50_us": round(pct(ev, 50) * 1e3, 1), "p99_us": round(pct(ev, 99) * 1e3, 1),
+                "GBps": round(nbytes / (pct(ev, 50) * 1e-3) / 1e9, 1),
+                "back_to_back_us": round(b2b_ms * 1e3, 1), "back_to_back_GBps": round(nbytes / (b2b_ms * 1e-3) / 1e9, 1)}
+
     if not plain:
         b.close()
         return {"nests": len(nests), "bytes": nbytes, "persistent_launches": st["launches"], "tasks": st["tasks"],
-                "wave_workers": st["workers"],
-                "batched_graph": {"p50_us": round(pct(ev_b, 50) * 1e3, 1), "p99_us": round(pct(ev_b, 99) * 1e3, 1),
-                                  "GBps": round(nbytes / (pct(ev_b, 50) * 1e-3) / 1e9, 1)}}
+                "wave_workers": st["workers"], "batched_graph": form(ev_b, b2b_g),
+                "batched_direct": form(ev_d, b2b_d), "direct_bit_identical": same_direct}
     b.set_io_ptrs(ins, [base_b + 8 * int(o) for o in oo[:-1]])
     wall_p, ev_p = timed(lambda: b.run_each(stream, graph=False), max(3, steps // 4), 1)
     got_p = out_b.cpu().numpy()
@@ -466,8 +490,8 @@ def batched_vs_plain(stream, steps=20, warmup=3, plain=True, verify=True):
         "nests": len(nests), "bytes": nbytes, "persistent_launches": st["launches"], "tasks": st["tasks"],
         "wave_workers": st["workers"],
         "plan_seconds": round(t_plan, 3),
-        "batched_graph": {"p50_us": round(pct(ev_b, 50) * 1e3, 1), "p99_us": round(pct(ev_b, 99) * 1e3, 1),
-                          "GBps": round(nbytes / (pct(ev_b, 50) * 1e-3) / 1e9, 1)},
+        "batched_graph": form(ev_b, b2b_g),
+        "batched_direct": form(ev_d, b2b_d), "direct_bit_identical": same_direct,
         "plain_one_launch_per_nest": {"p50_us": round(pct(ev_p, 50) * 1e3, 1),
                                       "GBps": round(nbytes / (pct(ev_p, 50) * 1e-3) / 1e9, 1)},
         "plain_launches_in_one_graph": {"p50_us": round(pct(ev_g, 50) * 1e3, 1),
