@@ -21,6 +21,8 @@
 
 namespace hp {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kTW = 64;  // output columns per workgroup
 // threads per workgroup: 8 per output row of the tile (256 for 32 rows, 512 for 64)
 constexpr int threads_of(int th) { return 8 * th; }
@@ -97,7 +99,7 @@ __device__ __forceinline__ uint32_t stencil_tile(uint32_t b, uint32_t nt, bool x
 template <int T, int TH>
 __global__ void __launch_bounds__(threads_of(TH)) k_stencil(const float* __restrict__ in, float* __restrict__ out,
                                                       long long R, long long C, uint32_t ntc, uint32_t nt, int xcd,
-                                                      int off32, float c0, float c1) {
+                                                      int off32, int vec4, float c0, float c1) {
   using G = Tile<T, TH>;
   constexpr int kThreads = threads_of(TH);
   extern __shared__ float lds[];
@@ -117,7 +119,37 @@ __global__ void __launch_bounds__(threads_of(TH)) k_stencil(const float* __restr
   constexpr int kLoads = (G::H * G::W + kThreads - 1) / kThreads;
   float v[kLoads];
   const bool whole = off32 && i0 >= 0 && j0 >= 0 && i0 + G::H <= R && j0 + G::W <= C;
-  if (whole) {
+  if (whole && vec4) {
+    // 16-byte loads: each row of the tile from its first 4-aligned column on (rows
+    // are 4-aligned when C is a multiple of 4); the words left and right of the tile
+    // are dropped, and the last vector of a row ends at most at column C - 1
+    constexpr int kSh = (4 - T % 4) % 4;         // j0 mod 4 (j0 = 64 tx - T)
+    constexpr int kN4 = (kSh + G::W + 3) / 4;    // vectors per row
+    constexpr int kV = (G::H * kN4 + kThreads - 1) / kThreads;
+    typedef const __attribute__((address_space(1))) f32x4 GV;
+    const float* __restrict__ base = in + (i0 * C + (j0 - kSh));
+    const uint32_t cu = (uint32_t)C;
+    f32x4 q[kV];
+#pragma unroll
+    for (int u = 0; u < kV; ++u) {
+      const int k = tid + u * kThreads;
+      const int r = k / kN4, c4 = k - (k / kN4) * kN4;
+      if (u + 1 < kV || k < G::H * kN4) q[u] = *(GV*)(base + (uint32_t)r * cu + 4u * (uint32_t)c4);
+    }
+#pragma unroll
+    for (int u = 0; u < kV; ++u) {
+      const int k = tid + u * kThreads;
+      const int r = k / kN4, c4 = k - (k / kN4) * kN4;
+      if (u + 1 < kV || k < G::H * kN4) {
+        float* row = buf0 + r * G::P;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 4 * c4 - kSh + e;
+          if (c >= 0 && c < G::W) row[c] = q[u][e];
+        }
+      }
+    }
+  } else if (whole) {
     const float* __restrict__ base = in + (i0 * C + j0);
     const uint32_t cu = (uint32_t)C;
 #pragma unroll
@@ -136,10 +168,12 @@ __global__ void __launch_bounds__(threads_of(TH)) k_stencil(const float* __restr
       v[u] = ok ? in[ok ? gi * C + gj : 0] : 0.f;
     }
   }
+  if (!(whole && vec4)) {
 #pragma unroll
-  for (int u = 0; u < kLoads; ++u) {
-    const int k = tid + u * kThreads;
-    if (k < G::H * G::W) buf0[(k / G::W) * G::P + (k - (k / G::W) * G::W)] = v[u];
+    for (int u = 0; u < kLoads; ++u) {
+      const int k = tid + u * kThreads;
+      if (k < G::H * G::W) buf0[(k / G::W) * G::P + (k - (k / G::W) * G::W)] = v[u];
+    }
   }
   __syncthreads();
   // interior cells (global 1..R-2, 1..C-2) in tile-local coordinates, clamped to the
@@ -170,7 +204,20 @@ __global__ void __launch_bounds__(threads_of(TH)) k_stencil(const float* __restr
   if constexpr (T >= 7) run(std::integral_constant<int, 7>{});
   if constexpr (T >= 8) run(std::integral_constant<int, 8>{});
   const float* fin = (T & 1) ? buf1 : buf0;
-  if (off32 && i0 + T + TH <= R && j0 + T + kTW <= C) {
+  if (off32 && vec4 && i0 + T + TH <= R && j0 + T + kTW <= C) {
+    // 16-byte stores: the output tile's rows start at column 64 tx
+    typedef __attribute__((address_space(1))) f32x4 GVW;
+    float* __restrict__ base = out + ((i0 + T) * C + (j0 + T));
+    const uint32_t cu = (uint32_t)C;
+    static_assert((TH * kTW / 4) % kThreads == 0, "whole passes over the output tile");
+#pragma unroll
+    for (int u = 0; u < TH * kTW / 4 / kThreads; ++u) {
+      const int k = tid + u * kThreads;
+      const int r = k / (kTW / 4), c = 4 * (k - (k / (kTW / 4)) * (kTW / 4));
+      const float* src = fin + (r + T) * G::P + c + T;
+      *(GVW*)(base + (uint32_t)r * cu + (uint32_t)c) = f32x4{src[0], src[1], src[2], src[3]};
+    }
+  } else if (off32 && i0 + T + TH <= R && j0 + T + kTW <= C) {
     float* __restrict__ base = out + ((i0 + T) * C + (j0 + T));
     const uint32_t cu = (uint32_t)C;
     static_assert((TH * kTW) % kThreads == 0, "whole passes over the output tile");
@@ -197,8 +244,11 @@ hp_status launch_t(const float* in, float* out, long long R, long long C, bool x
   constexpr size_t lds = 2 * Tile<T, TH>::kFloats * sizeof(float);
   // every offset within one tile (rows x columns with the widest ghost surface) fits 32 bits
   const int off32 = (unsigned long long)C * (TH + 2 * kMaxSweeps) + kTW + 2 * kMaxSweeps < (1ull << 32) ? 1 : 0;
+  // 16-byte loads and stores when every row starts 16-byte aligned
+  const int vec4 = (C % 4 == 0 && (reinterpret_cast<uintptr_t>(in) & 15u) == 0 &&
+                    (reinterpret_cast<uintptr_t>(out) & 15u) == 0) ? 1 : 0;
   hipLaunchKernelGGL((k_stencil<T, TH>), dim3(nt), dim3(threads_of(TH)), lds, st, in, out, R, C, ntc, nt, xcd ? 1 : 0,
-                     off32, c0, c1);
+                     off32, vec4, c0, c1);
   if (hipGetLastError() != hipSuccess) return hp::fail(HP_EDEVICE, "stencil launch failed");
   return HP_OK;
 }
