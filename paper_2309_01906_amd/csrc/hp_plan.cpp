@@ -161,7 +161,20 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
     --l;
   }
   if (lanes_left > 1) m->units[first_v][HP_AXIS_V] *= (uint32_t)lanes_left;
-  const uint64_t nw_target = bytes >= (256 << 10) ? 8 : bytes >= (16 << 10) ? 4 : bytes >= (4 << 10) ? 2 : 1;
+  // Waves per workgroup for the reduced block of one output.  A second wave pays
+  // only when one wave's share stays large: splitting a block over waves adds an LDS
+  // combine and a barrier per output, and with many outputs one-wave workgroups fill
+  // the chip anyway.  Measured over 2- and 3-level nests of 4 KiB to 256 KiB blocks
+  // (1,024 to 65,536 outputs): float blocks below 64 KiB and single-operator integer
+  // blocks below 128 KiB were fastest on one wave (up to 2x faster than 2-4 waves).
+  bool one_op = true;
+  for (int k = p + 1; k < d; ++k)
+    if (n->op[k] != n->op[p]) one_op = false;
+  const bool flt = n->dtype != HP_I32;
+  uint64_t nw_target;
+  if (flt) nw_target = bytes >= (256 << 10) ? 8 : bytes >= (64 << 10) ? 4 : 1;
+  else if (one_op) nw_target = bytes >= (128 << 10) ? 2 : 1;
+  else nw_target = bytes >= (256 << 10) ? 8 : bytes >= (16 << 10) ? 4 : bytes >= (4 << 10) ? 2 : 1;
   // waves of one workgroup: the next level outward, or the outermost lane level
   // the next level out whose units combine through a barrier and shared memory
   const uint32_t w_scope = combine_scope(HP_LP_BARRIER | HP_LP_LOCALMEM);
