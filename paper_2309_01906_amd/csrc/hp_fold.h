@@ -21,8 +21,10 @@ namespace hp {
 //   floats, G > kSeqFold: lane k adds partials k, k+64, ... the same way and the 64
 //     pairs merge in a xor butterfly;
 //   integers: the operators are exact, associative and commutative (ARG keeps the
-//     smaller index on ties), so any order gives the same result; several grid-
-//     spanning segments are folded by one lane, digits in index order.
+//     smaller index on ties), so any order gives the same result.  One grid-spanning
+//     segment: up to kSeqFold partials on one lane, more on a whole wave (lane k
+//     takes partials k, k+64, ..., then a xor butterfly); several grid-spanning
+//     segments are folded by one lane, digits in index order.
 constexpr long long kSeqFold = 16;
 
 // Partials are read kFoldBatch at a time, all loads issued before the first is
@@ -82,6 +84,24 @@ __device__ __forceinline__ long long fold_int_uniform_seq(const char* part, long
     for (int u = 0; u < kFoldBatch; ++u)
       if (k0 + u < G) a = IntT::merge(a, v[u], op);
   }
+  return IntT::emit(a, op);
+}
+
+// whole wave, one grid-spanning segment; every lane returns the result
+__device__ __forceinline__ long long fold_int_uniform_wave(const char* part, long long G, int op, int lane) {
+  IAcc a = IntT::identity(op);
+  constexpr int B = kFoldBatch / 2;
+  for (long long k0 = lane; k0 < G; k0 += (long long)B * kWave) {
+    IAcc v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + (long long)u * kWave < G) v[u] = IntT::get(part, k0 + (long long)u * kWave);
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (k0 + (long long)u * kWave < G) a = IntT::merge(a, v[u], op);
+  }
+#pragma unroll
+  for (int b = 0; b < 6; ++b) a = IntT::merge(a, IntT::shfl(a, 1 << b, lane), op);
   return IntT::emit(a, op);
 }
 
@@ -146,7 +166,8 @@ struct FoldTask {
 
 // Whether outputs of plan P fold on one lane each.
 __host__ __device__ inline bool fold_on_lane(const DevPlan& P) {
-  return P.dtype != HP_F32 && P.dtype != HP_BF16 ? true : P.gsplit <= kSeqFold;
+  const bool flt = P.dtype == HP_F32 || P.dtype == HP_BF16;
+  return P.gsplit <= kSeqFold || (!flt && P.gmode != GCOMB_UNIFORM);
 }
 
 // One wave runs one fold task.
@@ -156,8 +177,13 @@ __device__ __forceinline__ void fold_task(const DevPlan& P, const FoldTask& t, v
   if (t.wave) {
     const long long o = t.o0;
     const char* part = reinterpret_cast<const char*>(ws) + o * P.gsplit * kSlotBytes;
-    const double v = fold_flt_wave(part, P.gsplit, lane);
-    if (lane == 0) store_flt(P, out, o, v);
+    if (flt) {
+      const double v = fold_flt_wave(part, P.gsplit, lane);
+      if (lane == 0) store_flt(P, out, o, v);
+    } else {
+      const long long v = fold_int_uniform_wave(part, P.gsplit, P.seg[0].op, lane);
+      if (lane == 0) store_int(P, out, o, v);
+    }
     return;
   }
   if (lane >= t.n) return;

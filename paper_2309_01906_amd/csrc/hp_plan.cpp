@@ -200,16 +200,23 @@ static void auto_map(const hp_nest* n, int p, int chunk_last, hp_level_map* m, i
   }
   // anything further out runs on the grid, one workgroup per iteration
   for (int k = p; k <= l; ++k) m->scopes[k] = HP_SCOPE_G;
-  // too few outputs for the chip: split the outermost reducing level over the grid
+  // too few outputs for the chip: split the outermost reducing level over the grid.
+  // Measured: with 1,024 outputs of 256 KiB or 1 MiB a one-pass plan beat splitting
+  // each output in two (int32 46.2 vs 52.1 us, fp32 156.8 vs 163.7 us), so only
+  // fewer outputs than half the fill target are split.  Float splits run on twice
+  // the fill target of workgroups with at most 4 waves (1 to 512 outputs over 1 GiB:
+  // 162-169 us against 166-190 us on the fill target with 8 waves); integer splits
+  // on the fill target (8 or 64 outputs over 256 MiB: 50 us against 54-55 us on
+  // twice as many).
   if (l < p) {
     int64_t n_out = 1;
     for (int k = 0; k < p; ++k) n_out *= n->extent[k];
-    const int64_t target_wgs = kFillWorkgroups;
-    if (n_out < target_wgs) {
+    if (n_out < kFillWorkgroups / 2) {
+      if (flt && force_nw == 0 && m->units[w_level][HP_AXIS_W] > 4) m->units[w_level][HP_AXIS_W] = 4;
       const int64_t per = p == d - 1 ? cdiv(n->extent[p], chunk_last) : n->extent[p];
       const int64_t in_wg = (int64_t)(m->units[p][HP_AXIS_V] ? m->units[p][HP_AXIS_V] : 1) *
                             (int64_t)(m->units[p][HP_AXIS_W] ? m->units[p][HP_AXIS_W] : 1);
-      int64_t gf = cdiv(target_wgs, n_out);
+      int64_t gf = cdiv(flt ? 2 * kFillWorkgroups : kFillWorkgroups, n_out);
       const int64_t useful = cdiv(per, in_wg);
       const int64_t by_bytes = bytes / (64 << 10);  // keep >= 64 KiB of input per workgroup
       if (gf > useful) gf = useful;

@@ -329,6 +329,25 @@ def test_grid_combine_nested_segments():
         assert_match(got, x, ext, ops, what=f"nested {ops} {m}")
 
 
+def test_integer_grid_fold_on_lane_and_on_wave():
+    """One grid-spanning integer segment folds its partials on one lane up to 16
+    workgroups and on a whole wave beyond: both give the oracle's bits, ties of the
+    ARG operators included (values from a range of 7 repeat millions of times)."""
+    ext = (3, 1 << 21)
+    x = workloads.uniform_i32(79, ext, -3, 3)
+    dev = to_device(x)
+    for op in ("SUM", "MIN", "MAX", "ARGMIN", "ARGMAX"):
+        outs = []
+        for g in (4, 16, 17, 64, 1024, 4096):
+            got, info = gpu_reduce(x, ext, ("NONE", op), ["G", ("GWV", {"G": g, "W": 2})], dev=dev)
+            assert info["gsplit"] == g
+            assert_match(got, x, ext, ("NONE", op), what=f"{op} G={g}")
+            outs.append(got)
+        for o in outs[1:]:
+            np.testing.assert_array_equal(o, outs[0])
+        say("int fold", op, "bit-identical over G = 4 .. 4096")
+
+
 def test_plan_reuse_and_determinism():
     import paper_2309_01906_amd as hp
     x1 = workloads.normal_f32(77, (4, 1 << 20))
