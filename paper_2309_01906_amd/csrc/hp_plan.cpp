@@ -877,6 +877,19 @@ hp_status lower(const hp_nest* n, const hp_level_map* map_in, uint32_t flags, Lo
   I.kernel = dp.kernel;
   I.flat_block = flat_block;
   out->dp = dp;
+  // A float nest is a sum of sums (floats take SUM only), so each output's block is
+  // one contiguous run.  When the automatic plan iterates more than one level inside
+  // a thread it runs on the general kernel; the same block as one level may fit the
+  // lean kernel, which then takes it (3- and 4-level nests of 128-256 MiB: 1.04-1.5x
+  // faster in fp32, 1.14-2x in bf16, none slower).
+  if (is_float && !map_in && !flat_block && force_nw == 0 && dp.kernel != HP_KERNEL_LEAN && d - p >= 2 &&
+      chunk_last == 16 / elem_bytes(n->dtype) && !(flags & (HP_FLAG_GENERIC | HP_FLAG_SCALAR))) {
+    hp_nest v = *n;
+    v.depth = p + 1;
+    for (int l = p + 1; l < d; ++l) v.extent[p] *= n->extent[l];
+    Lowered one;
+    if (lower(&v, nullptr, flags, &one, 0, 0) == HP_OK && one.dp.kernel == HP_KERNEL_LEAN) *out = one;
+  }
   return HP_OK;
 }
 

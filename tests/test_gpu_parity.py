@@ -329,6 +329,25 @@ def test_grid_combine_nested_segments():
         assert_match(got, x, ext, ops, what=f"nested {ops} {m}")
 
 
+def test_sum_of_sums_collapsed_to_one_level():
+    """A float nest whose automatic plan would iterate two levels in a thread is run
+    as one level per output block: the result matches the oracle's nested sums, and
+    the explicit nested map gives the general kernel on the same data."""
+    import paper_2309_01906_amd as hp
+    for ext, dt in [((64, 16, 1024), hp.F32), ((32, 4, 8, 1024), hp.F32), ((128, 4, 2048), hp.BF16),
+                    ((48, 64, 512), hp.F32), ((5, 8, 8, 1024), hp.BF16), ((9, 4, 8, 512), hp.F32)]:
+        ops = ("NONE",) + ("SUM",) * (len(ext) - 1)
+        x = workloads.normal_f32(80, ext) if dt == hp.F32 else workloads.normal_bf16_bits(80, ext)
+        got, info = gpu_reduce(x, ext, ops)
+        assert info["depth"] == 2 and "lean" in info["kernel_name"], (ext, info["kernel_name"], info["map"])
+        assert_match(got, x, ext, ops, what=f"collapsed {ext}")
+        nested = ["G"] * (len(ext) - 2) + [("W", {"W": 2}), "V"]
+        got2, info2 = gpu_reduce(x, ext, ops, nested)
+        assert info2["depth"] == len(ext) and "lean" not in info2["kernel_name"]
+        assert_match(got2, x, ext, ops, what=f"nested {ext}")
+        say("collapsed", ext, info["kernel_name"], info["map"], "| nested", info2["kernel_name"])
+
+
 def test_integer_grid_fold_on_lane_and_on_wave():
     """One grid-spanning integer segment folds its partials on one lane up to 16
     workgroups and on a whole wave beyond: both give the oracle's bits, ties of the
