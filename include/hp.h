@@ -130,7 +130,10 @@ typedef struct hp_level_map {
 
 /* What the planner decided; filled by hp_plan_inspect / hp_plan_info. */
 typedef struct hp_plan_info {
-  int32_t depth;
+  int32_t depth;                   /* levels of the planned view: the nest's depth, or fewer when an
+                                      automatic float plan runs its reducing levels (all SUM, so each
+                                      output's block is contiguous) as one level, which it does when
+                                      that view fits the lean kernel and the nested one does not */
   int32_t out_dtype;               /* HP_I32 / HP_I64 / HP_F32 / HP_F64, or the element type of an ordered product */
   int64_t n_out;                   /* number of outputs */
   size_t out_bytes;                /* n_out * size of out_dtype */
