@@ -355,3 +355,43 @@ def test_level_table_and_automatic_maps_follow_it():
                 assert n_out < fill and i["gsplit"] > 1, (ext, ops, i["map"], i["units"])
         assert lanes <= by["V"]["units"] and waves <= by["W"]["units"], (ext, ops, i["units"])
     assert checked > 150
+
+
+def test_grid_split_and_wave_rules():
+    """The automatic map's measured rules: outputs below half the 2,048-workgroup fill
+    target split their outermost reducing level (floats over 4,096 workgroups of at most
+    4 waves, integers over 2,048), 1,024 outputs run in one pass, and unsplit float
+    plans of at most 1,024 outputs with 256-384 KiB blocks take 2 waves."""
+    one_f = hp.inspect((1, 1 << 28), ("NONE", "SUM"), hp.F32)
+    assert one_f["grid"] == 4096 and one_f["gsplit"] == 4096 and one_f["waves"] == 4
+    one_i = hp.inspect((1, 1 << 26), ("NONE", "MAX"), hp.I32)
+    assert one_i["grid"] == 2048 and one_i["gsplit"] == 2048
+    few = hp.inspect((256, 1 << 20), ("NONE", "SUM"), hp.F32)
+    assert few["grid"] == 4096 and few["gsplit"] == 16 and few["waves"] == 4
+    for ext, dt, ops in [((1024, 65536), hp.I32, ("NONE", "SUM")), ((1024, 1 << 18), hp.F32, ("NONE", "SUM"))]:
+        i = hp.inspect(ext, ops, dt)
+        assert i["gsplit"] == 1 and i["grid"] == 1024, (ext, i["units"])
+    assert hp.inspect((1024, 65536), ("NONE", "SUM"), hp.F32)["waves"] == 2
+    assert hp.inspect((1024, 131072), ("NONE", "SUM"), hp.BF16)["waves"] == 2
+    assert hp.inspect((1024, 98304), ("NONE", "SUM"), hp.F32)["waves"] == 8     # 384 KiB blocks
+    assert hp.inspect((1024, 1 << 18), ("NONE", "SUM"), hp.F32)["waves"] == 8   # 1 MiB blocks
+    assert hp.inspect((4096, 65536), ("NONE", "SUM"), hp.F32)["waves"] == 8     # 4,096 outputs
+    # the 4-level integer chain keeps 16 workgroups per output
+    c3 = hp.inspect((64, 128, 64, 64), ("NONE", "SUM", "MAX", "ARGMIN"), hp.I32)
+    assert c3["gsplit"] == 16 and c3["grid"] == 1024
+
+
+def test_sums_of_sums_run_as_one_level_when_that_is_lean():
+    for ext, dt in [((4096, 8, 1024), hp.F32), ((2048, 4, 8, 1024), hp.BF16), ((8192, 4, 2048), hp.F32)]:
+        ops = ("NONE",) + ("SUM",) * (len(ext) - 1)
+        i = hp.inspect(ext, ops, dt)
+        assert i["depth"] == 2 and i["kernel"] == hp.KERNEL_LEAN, (ext, i["kernel_name"])
+        assert i["n_out"] == ext[0] and i["in_elems"] == int(np.prod(ext))
+        nested = hp.inspect(ext, ops, dt, ["G"] * (len(ext) - 2) + [("W", {"W": 2}), "V"])
+        assert nested["depth"] == len(ext) and nested["kernel"] != hp.KERNEL_LEAN
+        assert hp.inspect(ext, ops, dt, flags=hp.FLAG_GENERIC)["depth"] == len(ext)
+    # already lean as nested (the headline): unchanged
+    c2 = hp.inspect((4096, 256, 256), ("NONE", "SUM", "SUM"), hp.F32)
+    assert c2["depth"] == 3 and c2["kernel"] == hp.KERNEL_LEAN
+    # integers keep their nested plan
+    assert hp.inspect((4096, 8, 1024), ("NONE", "SUM", "SUM"), hp.I32)["depth"] == 3
