@@ -448,8 +448,9 @@ hp_status hp_stream_read(const void* d_in, size_t bytes, float* d_out, int32_t g
  * lanes), then to the level with HP_LP_BARRIER and HP_LP_LOCALMEM (a workgroup's
  * waves, through LDS), and last to the grid, which has neither (a second kernel
  * folds its partials); the unit counts bound the lanes and waves it hands out;
- * `fill_workgroups` is the grid size below which the outermost reducing level is
- * also split over workgroups.  HP_LP_SHARED_CACHE (an XCD's L2) pays only when
+ * `fill_workgroups` sets the grid split: a nest with fewer outputs than half of it
+ * also splits its outermost reducing level over workgroups, to about twice that
+ * many workgroups for float inputs and that many for int32.  HP_LP_SHARED_CACHE (an XCD's L2) pays only when
  * several workgroups read the same data; a nested reduction reads every element
  * once, so the automatic map never places a level on X (explicit maps may).
  * hp_level_table copies the rows, outermost first (G, X, W, V, L), into out
