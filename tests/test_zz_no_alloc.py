@@ -35,6 +35,10 @@ CASES = [
     # no grid split, ragged flat blocks
     ("f32", (300, 4099), ("NONE", "SUM"), (17, 1001)),
     ("i32", (64, 5000), ("NONE", "MIN"), (5, 77)),
+    # one-output integer nest whose partials fold on a whole wave, then a smaller one
+    ("i32", (1, 1 << 22), ("NONE", "MAX"), (3, 1 << 20)),
+    # float sum of sums planned as one level, then a smaller one
+    ("f32", (64, 16, 1024), ("NONE", "SUM", "SUM"), (5, 16, 1024)),
 ]
 
 
