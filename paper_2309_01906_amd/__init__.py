@@ -145,8 +145,11 @@ def kernel_name(inf: PlanInfo, ops=None) -> str:
         return "hp::k_ordered<2, 8>" if inf.out_dtype == AFFINE64 else "hp::k_ordered<4, 4>"
     if inf.kernel == KERNEL_INT_CHAIN:
         return f"hp::k_nest_i32_chain<{OP_TEMPLATE[_op(ops[-1])] if ops else '?'}, {inf.nseg}>"
-    if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG, KERNEL_INT_DEEP):
-        kind = {KERNEL_INT_FLAT: "flat", KERNEL_INT_SEG: "seg", KERNEL_INT_DEEP: "deep"}[inf.kernel]
+    if inf.kernel == KERNEL_INT_DEEP:
+        bounds = "3, 4" if inf.depth <= 4 and inf.nseg <= 3 else f"{MAX_DEPTH}, {MAX_DEPTH}"
+        return f"hp::k_nest_i32_deep<{c}, {bounds}>"
+    if inf.kernel in (KERNEL_INT_FLAT, KERNEL_INT_SEG):
+        kind = {KERNEL_INT_FLAT: "flat", KERNEL_INT_SEG: "seg"}[inf.kernel]
         return f"hp::k_nest_i32_{kind}<{c}>"
     t = "bf16" if inf.in_bytes == 2 * inf.in_elems else "f32"
     if inf.kernel == KERNEL_LEAN:
